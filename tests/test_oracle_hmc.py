@@ -1,0 +1,78 @@
+"""Leapfrog and Hamiltonian of the oracle (Sections 2.1-2.2)."""
+import numpy as np
+import pytest
+
+import fzw_inputs as fi
+from oracle import hmc
+from tests.helpers import mock_case
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def test_leapfrog_harmonic_oscillator_closed_form():
+    """For U = q^2/2 and unit mass one kick-drift-kick step is the linear map
+    [[1 - e^2/2, e], [-e (1 - e^2/4), 1 - e^2/2]] (Hairer, Lubich & Wanner,
+    Geometric Numerical Integration, Sec. I.1); n steps are its n-th power."""
+    eps, n = 0.1, 37
+    q0, p0 = np.array([0.3, -1.2]), np.array([0.8, 0.1])
+    step = np.array([[1 - eps ** 2 / 2, eps], [-eps * (1 - eps ** 2 / 4), 1 - eps ** 2 / 2]])
+    mat = np.linalg.matrix_power(step, n)
+    gfn = lambda q, u: (0.5 * float(q @ q), q.copy(), np.zeros_like(u))
+    q, u, p, pu, h0, h1 = hmc.leapfrog(gfn, q0, np.zeros(1), p0, np.zeros(1), 1.0, 1.0, eps, n)
+    want = mat @ np.stack([q0, p0])
+    assert np.allclose(q, want[0], atol=1e-14)
+    assert np.allclose(p, want[1], atol=1e-14)
+    # energy error of leapfrog on the oscillator is O(eps^2)
+    assert abs(h1 - h0) < eps ** 2 * h0
+
+
+def _potential(name="c0fd"):
+    w, m, nu_t, nu_e, counts = mock_case(name)
+    ch = w.chains[0]
+    tying = w.free
+    mu = np.full(len(tying), fi.PRIOR_MU_ALPHA)
+    sig = np.full(len(tying), fi.PRIOR_SIGMA_ALPHA)
+    u0 = np.log(np.array([ch.bias[r[0], c] for r, c in tying]))
+    gfn = lambda q, u: hmc.potential_and_grad(m, q, u, ch.bias, tying, mu, sig, counts)
+    return gfn, nu_t, u0
+
+
+def test_leapfrog_reversible_on_the_model():
+    gfn, nu, u = _potential()
+    rng = np.random.default_rng(4)
+    p = rng.standard_normal(nu.shape)
+    pu = rng.standard_normal(u.shape)
+    minv_u = np.full(u.shape, 1e-3)
+    q1, u1, p1, pu1, h0, h1 = hmc.leapfrog(gfn, nu, u, p, pu, 1.0, minv_u, 2e-3, 6)
+    q2, u2, p2, pu2, _, _ = hmc.leapfrog(gfn, q1, u1, -p1, -pu1, 1.0, minv_u, 2e-3, 6)
+    assert np.allclose(q2, nu, atol=1e-10)
+    assert np.allclose(u2, u, atol=1e-12)
+    assert np.allclose(-p2, p, atol=1e-8)
+
+
+def test_leapfrog_energy_error_second_order_smooth_potential():
+    """On a smooth anharmonic potential, halving the step at a fixed trajectory
+    length divides |dH| by about 4.  (The model's own potential is only
+    piecewise smooth: CIC weights have kinks at cell faces and the spherical
+    collapse a hinge, so its energy error also carries jumps at crossings.)"""
+    rng = np.random.default_rng(5)
+    q0 = rng.standard_normal(50)
+    p0 = rng.standard_normal(50)
+    gfn = lambda q, u: (float(np.sum(q ** 4 / 4 + q ** 2 / 2)), q ** 3 + q, np.zeros_like(u))
+    errs = []
+    for eps, n in ((0.04, 25), (0.02, 50), (0.01, 100)):
+        *_, h0, h1 = hmc.leapfrog(gfn, q0, np.zeros(1), p0, np.zeros(1), 1.0, 0.0, eps, n)
+        errs.append(abs(h1 - h0))
+    assert 3.0 < errs[0] / errs[1] < 5.0
+    assert 3.0 < errs[1] / errs[2] < 5.0
+
+
+def test_potential_gradient_includes_priors():
+    """dU/dnu = -dlogL/dnu + nu and dU/du adds (u - mu)/sigma^2 (central differences)."""
+    gfn, nu, u = _potential()
+    pot, gnu, gu = gfn(nu, u)
+    for i in range(len(u)):
+        e = np.zeros_like(u)
+        e[i] = 1e-6
+        fd = (gfn(nu, u + e)[0] - gfn(nu, u - e)[0]) / 2e-6
+        assert fd == pytest.approx(gu[i], rel=1e-5, abs=1e-6 * np.abs(gu).max())

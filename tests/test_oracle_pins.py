@@ -1,0 +1,430 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage or closed form it checks.  None of them re-types
+the oracle's own formula: they use worked limits, analytic fields, printed
+table values, library distributions or brute force.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+import fzw_inputs as fi
+from oracle import cosmology
+from oracle.model import Grid, Model, Settings, nb_loglike, PAIRS
+from oracle.stats import power_spectrum
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _model(n=16, box=125.0, **kw):
+    cos = fi.Cosmo(**{k: v for k, v in kw.items() if k in fi.Cosmo.__dataclass_fields__})
+    web = fi.Web(**{k: v for k, v in kw.items() if k in fi.Web.__dataclass_fields__})
+    ch = fi.Chain(n, box, fi.four_class_table(), 1.0, (9, n))
+    return Model(Settings.from_workload(cos, web, ch))
+
+
+def _coords(n, box):
+    x = np.arange(n) * box / n
+    return np.meshgrid(x, x, x, indexing="ij")
+
+
+# ------------------------------------------------------------ printed values
+def test_table_cases_nyquist_frequencies():
+    """Table 'cases': k_nyq = pi/dL and the non-isotropic sqrt(3) k_nyq, as
+    printed to two decimals, equal the largest |k_x| and |k| of the oracle's
+    wave-vector grid on a 128^3 mesh."""
+    gold = json.load(open(os.path.join(GOLD, "table_cases.json")))
+    for name in ("TEST1", "TEST2", "TEST3"):
+        t = gold[name]
+        assert t["L"] / gold["N"] == pytest.approx(t["dL"])
+        g = Grid(gold["N"], t["L"])
+        kmax = float(np.abs(g.k[0]).max())
+        assert round(kmax, 2) == pytest.approx(t["k_nyq"], abs=1e-9)
+        assert round(float(g.kmag.max()), 2) == pytest.approx(t["k_nyq_noniso"], abs=0.011)
+
+
+def test_bias_tables_match_printed_values():
+    """Tables 'values' and 'values3' as printed feed the workloads."""
+    v = json.load(open(os.path.join(GOLD, "table_values.json")))
+    assert tuple(v["TEST1"]["alpha"]) == fi.TEST1_ALPHA
+    assert tuple(v["TEST1"]["beta"]) == fi.TEST1_BETA
+    assert tuple(v["TEST2"]["alpha"]) == fi.TEST2_ALPHA
+    v3 = json.load(open(os.path.join(GOLD, "table_values3.json")))
+    assert [tuple(r) for r in v3["rows"]] == [tuple(r) for r in fi.TEST3_TABLE]
+    t = fi.sixteen_region_table()
+    assert np.allclose(t[:, fi.COL_EPS], -np.array(v3["rows"])[:, 2])
+    assert np.allclose(t[:, fi.COL_RHO], np.array(v3["rows"])[:, 3])
+
+
+# ------------------------------------------------------------ power spectrum
+def test_bbks_small_scale_limit():
+    """The transfer function tends to 1 on large scales."""
+    assert cosmology.bbks_transfer(1e-7, 0.31, 0.68) == pytest.approx(1.0, abs=1e-5)
+
+
+def test_sigma8_normalisation_independent_quadrature():
+    """The amplitude reproduces sigma8 = 0.81 when the top-hat variance is
+    re-integrated in linear k with Simpson's rule (a different integrator and
+    variable than the oracle's)."""
+    cos = fi.Cosmo()
+    amp = cosmology.power_amplitude(cos)
+    k = np.linspace(1e-6, 60.0, 2_000_001)
+    integrand = k * k * cosmology.linear_power(k, cos, amp) * cosmology.tophat_window(8.0 * k) ** 2
+    s2 = integrate.simpson(integrand, x=k) / (2 * np.pi ** 2)
+    assert np.sqrt(s2) == pytest.approx(0.81, rel=2e-4)
+
+
+def test_white_noise_filter_recovers_input_power():
+    """Appendix A: the linear density has covariance dx^-3 F^-1 P F, so the
+    binned estimate (dx^3/N^3)|rfftn delta_L|^2 averages to P(k)."""
+    m = _model(n=32, box=250.0)
+    edges = np.linspace(0.03, 0.35, 9)
+    ratios = []
+    for seed in range(24):
+        nu = np.random.default_rng(seed).standard_normal((32, 32, 32))
+        dl = m.g.irfft(m.linear_density_hat(nu))
+        k, pk, cnt = power_spectrum(dl, 250.0, edges)
+        ratios.append(pk / cosmology.linear_power(k, m.s, m.amp))
+    r = np.array(ratios)
+    mean = r.mean(0)
+    err = r.std(0) / np.sqrt(r.shape[0])
+    # bins are narrow enough that P varies little across each one
+    assert np.all(np.abs(mean - 1.0) < 4 * err + 0.03), (mean, err)
+    assert abs(np.average(mean, weights=1 / err ** 2) - 1.0) < 0.02
+
+
+def test_white_noise_filter_single_mode_is_eigenfunction():
+    """A single Fourier mode is an eigenfunction of the filter with eigenvalue
+    h(k) = sqrt(P(k)/dx^3)."""
+    n, box = 16, 125.0
+    m = _model(n, box)
+    x, y, z = _coords(n, box)
+    kv = 2 * np.pi / box * np.array([1, 2, 3])
+    nu = np.cos(kv[0] * x + kv[1] * y + kv[2] * z)
+    dl = m.g.irfft(m.linear_density_hat(nu))
+    kk = np.linalg.norm(kv)
+    h = np.sqrt(cosmology.linear_power(kk, m.s, m.amp) / (box / n) ** 3)
+    assert np.allclose(dl, h * nu, atol=1e-12 * h)
+
+
+# --------------------------------------------------------------------- ALPT
+def _inject(m, dl):
+    return m.g.rfft(dl)
+
+
+def test_zeldovich_plane_wave():
+    """Pure 2LPT (r_s -> 0 makes K = 1): delta_L = A cos(k x) has S2 = 0 and the
+    Zel'dovich displacement Psi_x = -(A/k) sin(k x), Psi_y = Psi_z = 0."""
+    n, box, a = 16, 125.0, 0.7
+    m = _model(n, box, r_s=0.0)
+    x, y, z = _coords(n, box)
+    k = 2 * np.pi / box * 2
+    psi, lpt = m.alpt(_inject(m, a * np.cos(k * x)))
+    assert np.allclose(lpt["s2"], 0.0, atol=1e-13)
+    assert np.allclose(psi[0], -(a / k) * np.sin(k * x), atol=1e-11)
+    assert np.allclose(psi[1:], 0.0, atol=1e-11)
+
+
+def test_2lpt_crossed_waves():
+    """Pure 2LPT: delta_L = A cos(kx) + B cos(ky) gives S2 = A B cos kx cos ky and
+    Psi_x = -(A/k) sin kx - (3/14)(A B / k) sin kx cos ky (second order with
+    D2 = -3/7, from lap phi2 = S2, Psi2 = D2 grad phi2)."""
+    n, box, a, b = 16, 125.0, 0.6, 0.4
+    m = _model(n, box, r_s=0.0)
+    x, y, z = _coords(n, box)
+    k = 2 * np.pi / box * 2
+    psi, lpt = m.alpt(_inject(m, a * np.cos(k * x) + b * np.cos(k * y)))
+    assert np.allclose(lpt["s2"], a * b * np.cos(k * x) * np.cos(k * y), atol=1e-12)
+    want = -(a / k) * np.sin(k * x) - (3.0 / 14.0) * (a * b / k) * np.sin(k * x) * np.cos(k * y)
+    assert np.allclose(psi[0], want, atol=1e-11)
+    want_y = -(b / k) * np.sin(k * y) - (3.0 / 14.0) * (a * b / k) * np.sin(k * y) * np.cos(k * x)
+    assert np.allclose(psi[1], want_y, atol=1e-11)
+
+
+def test_spherical_collapse_one_dimensional_wave():
+    """Pure spherical collapse (r_s -> infinity makes K = 0 for k != 0): for
+    delta_L = A cos(k x) the displacement is the zero-mean antiderivative of
+    3 (sqrt(1 - 2 delta_L / 3) - 1).  The reference integrates that closed-form
+    function with a fine 1-D spectral antiderivative."""
+    n, box, a = 32, 250.0, 1.0
+    m = _model(n, box, r_s=1e9)
+    x, y, z = _coords(n, box)
+    k = 2 * np.pi / box
+    psi, _ = m.alpt(_inject(m, a * np.cos(k * x)))
+    fine = 4096
+    xf = np.arange(fine) * box / fine
+    d = 3 * (np.sqrt(1 - 2 * a * np.cos(k * xf) / 3) - 1)
+    dh = np.fft.rfft(d)
+    kk = 2 * np.pi / box * np.arange(dh.size)
+    anti = np.zeros_like(dh)
+    anti[1:] = dh[1:] / (1j * kk[1:])
+    ref = np.fft.irfft(anti, n=fine)[:: fine // n]
+    assert np.allclose(psi[0][:, 0, 0], ref, atol=1e-6)
+    assert np.allclose(psi[1:], 0.0, atol=1e-10)
+
+
+def test_spherical_collapse_small_amplitude_matches_zeldovich():
+    """For small delta_L the spherical-collapse divergence -> -delta_L, so the
+    displacement matches the Zel'dovich one to second order in A."""
+    n, box, a = 16, 125.0, 1e-4
+    m = _model(n, box, r_s=1e9)
+    x, y, z = _coords(n, box)
+    k = 2 * np.pi / box * 3
+    psi, _ = m.alpt(_inject(m, a * np.cos(k * y)))
+    assert np.allclose(psi[1], -(a / k) * np.sin(k * y), atol=5e-3 * a / k)
+
+
+def test_alpt_displacement_curl_free_for_sc():
+    """The spherical-collapse displacement is a gradient: d_i Psi_j = d_j Psi_i
+    (checked with an 8th-order finite-difference stencil on a smooth field)."""
+    n, box = 32, 250.0
+    m = _model(n, box, r_s=1e9)
+    x, y, z = _coords(n, box)
+    k = 2 * np.pi / box
+    dl = 0.5 * np.cos(k * x + 0.3) * np.cos(k * y) + 0.3 * np.sin(k * (y + z))
+    psi, _ = m.alpt(_inject(m, dl))
+    dx = box / n
+    c = [4 / 5, -1 / 5, 4 / 105, -1 / 280]
+
+    def d(f, ax):
+        return sum(ci * (np.roll(f, -(i + 1), ax) - np.roll(f, i + 1, ax)) for i, ci in enumerate(c)) / dx
+
+    scale = np.abs(psi).max() / dx
+    for i in range(3):
+        for j in range(i + 1, 3):
+            assert np.abs(d(psi[j], i) - d(psi[i], j)).max() < 2e-3 * scale
+
+
+# ---------------------------------------------------------------------- CIC
+def test_cic_unperturbed_lattice_is_uniform():
+    m = _model(16)
+    rho = m.cic(m.positions(np.zeros((3, 16, 16, 16))))
+    assert np.array_equal(rho, np.ones((16, 16, 16)))
+
+
+def test_cic_constant_shift_is_uniform_and_mass_conserved():
+    m = _model(16)
+    psi = np.zeros((3, 16, 16, 16))
+    psi[0], psi[1], psi[2] = 3.3, -17.9, 0.45 * m.g.dx
+    rho = m.cic(m.positions(psi))
+    assert np.allclose(rho, 1.0, atol=1e-12)
+    rnd = np.random.default_rng(0).normal(scale=20.0, size=(3, 16, 16, 16))
+    assert m.cic(m.positions(rnd)).sum() == pytest.approx(16 ** 3, rel=1e-13)
+
+
+def test_cic_single_particle_weights_and_wrap():
+    """Trilinear weights of one particle, including the periodic wrap, by hand."""
+    m = _model(8, box=8.0)
+    rho = m.cic(np.array([2.25, 3.5, 7.75]).reshape(3, 1, 1, 1))
+    want = np.zeros((8, 8, 8))
+    for ix, wx in ((2, 0.75), (3, 0.25)):
+        for iy, wy in ((3, 0.5), (4, 0.5)):
+            for iz, wz in ((7, 0.25), (0, 0.75)):
+                want[ix, iy, iz] += wx * wy * wz
+    assert np.allclose(rho, want, atol=1e-15)
+
+
+def test_cic_brute_force_small_mesh():
+    """Vectorised CIC equals a plain loop over particles and the 8 nodes."""
+    n = 4
+    m = _model(n, box=4.0)
+    rng = np.random.default_rng(3)
+    psi = rng.normal(scale=1.3, size=(3, n, n, n)).clip(-8, 8)
+    pos = m.positions(psi)
+    want = np.zeros((n, n, n))
+    for i in range(n):
+        for j in range(n):
+            for l in range(n):
+                s = pos[:, i, j, l]
+                for cx in range(-12, n + 13):
+                    for cy in range(-12, n + 13):
+                        for cz in range(-12, n + 13):
+                            w = 1.0
+                            for sc, c in zip(s, (cx, cy, cz)):
+                                w *= max(0.0, 1.0 - abs(sc - c))
+                            if w > 0:
+                                want[cx % n, cy % n, cz % n] += w
+    assert np.allclose(m.cic(pos), want, atol=1e-12)
+
+
+def test_rsd_plane_parallel_displaces_only_the_line_of_sight():
+    """Section 2.9 with a plane-parallel line of sight along z and b_v = 1: a
+    uniform displacement along z is amplified by (1+f); x and y are untouched."""
+    n = 8
+    m = _model(n, box=8.0, rsd_axis=2)
+    psi = np.zeros((3, n, n, n))
+    psi[2] = 0.5
+    psi[0] = 0.25
+    pos = m.positions(psi)
+    grid = np.indices((n, n, n), dtype=float)
+    assert np.allclose(pos[2] - grid[2], 0.5 * (1 + m.s.f_growth))
+    assert np.allclose(pos[0] - grid[0], 0.25)
+
+
+# ---------------------------------------------------------------- web tensors
+def test_tidal_tensor_of_plane_wave_is_rank_one():
+    """Phi-web with no smoothing: delta = A cos(k.x) has T = A cos(k.x) khat khat^T,
+    so the sorted eigenvalues are {A cos, 0, 0} up to order."""
+    n, box, a = 16, 100.0, 0.8
+    m = _model(n, box)
+    x, y, z = _coords(n, box)
+    kv = 2 * np.pi / box * np.array([1.0, 2.0, 0.0])
+    ph = kv[0] * x + kv[1] * y
+    t6 = m.web_tensors(m.g.rfft(a * np.cos(ph)))[0]
+    kh = kv / np.linalg.norm(kv)
+    for (i, j), c in zip(PAIRS, t6):
+        assert np.allclose(c, a * np.cos(ph) * kh[i] * kh[j], atol=1e-12)
+    lam, _ = m.eigen(t6)
+    want = np.sort(np.stack([a * np.cos(ph).ravel(), 0 * ph.ravel(), 0 * ph.ravel()], 1), 1)[:, ::-1]
+    assert np.allclose(lam, want, atol=1e-12)
+
+
+def test_tidal_tensor_axis_separable_field_is_diagonal():
+    n, box = 16, 100.0
+    m = _model(n, box)
+    x, y, z = _coords(n, box)
+    k = 2 * np.pi / box * 2
+    amps = (0.3, -0.5, 0.9)
+    dl = amps[0] * np.cos(k * x) + amps[1] * np.cos(k * y) + amps[2] * np.cos(k * z)
+    t6 = m.web_tensors(m.g.rfft(dl))[0]
+    for c, v, a in zip(t6[:3], (x, y, z), amps):
+        assert np.allclose(c, a * np.cos(k * v), atol=1e-12)
+    for c in t6[3:]:
+        assert np.allclose(c, 0.0, atol=1e-12)
+
+
+def test_delta_web_tensor_is_minus_scaled_hessian():
+    """delta-web (no smoothing): T_ij = -ell^2 d_i d_j delta; for A cos(kx),
+    T_xx = ell^2 k^2 A cos(kx)."""
+    n, box, a, ell = 16, 100.0, 0.4, 2.0
+    m = _model(n, box, kinds=(fi.WEB_DELTA,), smooth_r=(0.0,), ell=(ell,))
+    x, y, z = _coords(n, box)
+    k = 2 * np.pi / box * 3
+    t6 = m.web_tensors(m.g.rfft(a * np.cos(k * x)))[0]
+    assert np.allclose(t6[0], ell ** 2 * k ** 2 * a * np.cos(k * x), atol=1e-12)
+    assert np.allclose(np.stack(t6[1:]), 0.0, atol=1e-12)
+
+
+def test_gaussian_smoothing_of_tensor_single_mode():
+    """A Gaussian smoothing of radius R multiplies a single mode by exp(-k^2 R^2/2)."""
+    n, box, a, r = 16, 100.0, 0.4, 8.0
+    m = _model(n, box, smooth_r=(r,))
+    x, y, z = _coords(n, box)
+    k = 2 * np.pi / box * 2
+    t6 = m.web_tensors(m.g.rfft(a * np.cos(k * z)))[0]
+    assert np.allclose(t6[2], np.exp(-0.5 * k * k * r * r) * a * np.cos(k * z), atol=1e-12)
+
+
+def test_eigenvalues_invariants_and_rotations():
+    """Appendix B: sum of eigenvalues = trace (I1), product = determinant (I3),
+    and a rotated diagonal matrix gives back its diagonal, sorted descending."""
+    rng = np.random.default_rng(5)
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    d = np.array([0.7, -0.2, 0.1])
+    mat = q @ np.diag(d) @ q.T
+    t6 = [np.full((1, 1, 1), mat[i, j]) for (i, j) in PAIRS]
+    lam, _ = _model(4, 4.0).eigen(t6)
+    assert np.allclose(lam[0], [0.7, 0.1, -0.2], atol=1e-14)
+    a = rng.normal(size=(50, 3, 3))
+    a = a + a.transpose(0, 2, 1)
+    t6 = [a[:, i, j].reshape(50, 1, 1) for (i, j) in PAIRS]
+    lam, _ = _model(4, 4.0).eigen(t6)
+    assert np.all(np.diff(lam, axis=1) <= 0)
+    assert np.allclose(lam.sum(1), np.trace(a, axis1=1, axis2=2))
+    assert np.allclose(lam.prod(1), np.linalg.det(a))
+
+
+# --------------------------------------------------------- fuzzy memberships
+def test_memberships_partition_of_unity_and_hard_limit():
+    """Eq. 'soft_cweb_p' memberships are non-negative and sum to one; with a huge
+    steepness they become one-hot on the class W = number of eigenvalues above
+    the threshold (Eq. 'hard_cweb'), W = 0..3 -> void, sheet, filament, knot."""
+    rng = np.random.default_rng(7)
+    lam = np.sort(rng.normal(scale=0.5, size=(5000, 3)), 1)[:, ::-1]
+    m = _model(4, 4.0)
+    _, p = m.memberships(lam)
+    assert np.all(p >= -1e-15)
+    assert np.allclose(p.sum(0), 1.0)
+    hard = _model(4, 4.0, steepness=1e6)
+    _, ph = hard.memberships(lam)
+    w_class = (lam > hard.s.lambda_th).sum(1)
+    ok = np.abs(lam - hard.s.lambda_th).min(1) > 1e-3
+    assert ok.sum() > 4000
+    onehot = np.eye(4)[w_class]
+    assert np.allclose(ph.T[ok], onehot[ok], atol=1e-12)
+
+
+def test_sixteen_regions_partition_of_unity():
+    rng = np.random.default_rng(8)
+    m = _model(4, 4.0)
+    _, pa = m.memberships(np.sort(rng.normal(size=(100, 3)), 1)[:, ::-1])
+    _, pb = m.memberships(np.sort(rng.normal(size=(100, 3)), 1)[:, ::-1])
+    p16 = Model.regions([pa, pb])
+    assert p16.shape == (16, 100)
+    assert np.allclose(p16.sum(0), 1.0)
+    assert np.allclose(p16[4 * 2 + 1], pa[2] * pb[1])
+
+
+# ---------------------------------------------------------------- likelihood
+def test_negative_binomial_matches_scipy():
+    """Section 2.7: Gamma(beta, nbar/beta) x Poisson is NB(n; r=beta, p=beta/(beta+nbar))."""
+    rng = np.random.default_rng(11)
+    n = rng.integers(0, 80, size=2000).astype(float)
+    nbar = np.exp(rng.normal(0.0, 1.5, size=2000))
+    beta = rng.uniform(0.5, 20.0, size=2000)
+    ell, _ = nb_loglike(n, np.log(nbar), beta)
+    ref = stats.nbinom.logpmf(n, beta, beta / (beta + nbar))
+    assert np.allclose(ell, ref, rtol=1e-10, atol=1e-10)
+
+
+def test_negative_binomial_poisson_limit():
+    """beta -> infinity recovers the Poisson likelihood."""
+    n = np.arange(0, 30, dtype=float)
+    nbar = np.full_like(n, 3.7)
+    ell, _ = nb_loglike(n, np.log(nbar), np.full_like(n, 1e9))
+    assert np.allclose(ell, stats.poisson.logpmf(n, nbar), atol=1e-6)
+
+
+def test_gamma_poisson_mock_moments():
+    """Mock counts have mean nbar and variance nbar + nbar^2/beta."""
+    rng = np.random.default_rng(12)
+    nbar = np.full(400_000, 2.0)
+    c = fi.gamma_poisson_counts(nbar, np.full_like(nbar, 3.0), rng).astype(float)
+    assert c.mean() == pytest.approx(2.0, rel=0.01)
+    assert c.var() == pytest.approx(2.0 + 4.0 / 3.0, rel=0.02)
+
+
+def _counts(m, seed=0, mean=1.0):
+    rng = np.random.default_rng(seed)
+    return rng.poisson(mean, size=(m.s.n,) * 3).astype(np.uint16)
+
+
+def test_normalisation_sums_to_number_of_tracers():
+    """Eq. 'local_bias': C is fixed by sum nbar = sum n* = N_tr."""
+    m = _model(16)
+    nu = np.random.default_rng(1).standard_normal((16,) * 3)
+    c = _counts(m)
+    st = m.forward(nu, fi.four_class_table(), c)
+    assert st["nbar"].sum() == pytest.approx(float(c.sum()), rel=1e-12)
+
+
+def test_equal_regions_make_the_web_irrelevant():
+    """With identical parameters in every region the memberships drop out and
+    nbar = N_tr f / sum f with f = x^alpha exp(-(x/rho)^eps), x = 1 + delta."""
+    m = _model(16)
+    nu = np.random.default_rng(2).standard_normal((16,) * 3)
+    c = _counts(m)
+    tab = fi.four_class_table(alpha=(1.2,) * 4, eps=-1.3, rho=0.3, beta=4.0)
+    # no tracers where the model density underflows (scipy's pmf would be -inf)
+    c[m.forward(nu, tab)["rho"] < 0.05] = 0
+    st = m.forward(nu, tab, c)
+    x = np.maximum(st["rho"].ravel(), 1e-6)
+    f = x ** 1.2 * np.exp(-(x / 0.3) ** -1.3)
+    want = c.sum() * f / f.sum()
+    assert np.allclose(st["nbar"], want, rtol=1e-10, atol=1e-300)
+    ref = stats.nbinom.logpmf(c.ravel(), 4.0, 4.0 / (4.0 + want))
+    assert st["logl"] == pytest.approx(ref.sum(), rel=1e-10)
