@@ -1,0 +1,184 @@
+"""Throughput of the forward model + hand-written adjoint (logL gradient
+evaluations per second) on one MI355X, with the roofline of the dominant kernel
+class and the FP64 CPU oracle timed beside it.
+
+Workload (default): 256^3 mesh, L = 1000 Mpc/h, Phi-web (R=8) x delta-web (R=2),
+16 regions, plane-parallel RSD along z, mean count 2, NB dispersion 3; seeded
+synthetic white noise and synthetic counts.  One step = one forward + adjoint
+(value_and_grad) of that chain.  Also reported: the same step with 4 identical
+256^3 chains batched in one plan (grads/s counts every chain).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, 8 TB/s
+
+
+def _plan(w, chains, Plan, CosmoParams, WebParams):
+    c = w.cosmo
+    cosmo = CosmoParams(c.omega_m, c.h, c.sigma8, c.n_s, c.d1, c.f_growth, c.r_s, c.rsd_axis, c.tau_sc,
+                        c.x_floor)
+    web = WebParams(w.web.kinds, w.web.smooth_r, w.web.ell, w.web.steepness, w.web.lambda_th)
+    return Plan([ch.n for ch in chains], [ch.box for ch in chains], cosmo, web)
+
+
+def _time_steps(plan, nu, bias, out, steps, torch):
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(plan.stream)
+    for _ in range(steps):
+        plan.value_and_grad(nu, bias, out)
+    ev1.record(plan.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return ev0.elapsed_time(ev1) / 1e3, wall
+
+
+def cpu_baseline(w):
+    """The FP64 oracle (as it stands) on a bounded sample: one forward + adjoint
+    of the same model at 128^3 with the same cell size, scaled by the 8x voxel
+    count to the 256^3 step."""
+    import numpy as np
+    import fzw_inputs as fi
+    from oracle import model as om
+    ncpu = os.cpu_count() or 1
+    om.set_workers(ncpu)
+    ws = fi.small_variant(w, 128)
+    ch = ws.chains[0]
+    m = om.Model(om.Settings.from_workload(ws.cosmo, ws.web, ch))
+    nu = fi.white_noise(ch, fi.ROLE_EVAL_NU)
+    counts = fi.timing_counts(ch)
+    t0 = time.perf_counter()
+    st = m.forward(nu, ch.bias, counts)
+    m.adjoint(st)
+    dt = time.perf_counter() - t0
+    scale = (w.chains[0].n / 128) ** 3
+    return {"value": 1.0 / (dt * scale), "unit": "grads/s", "cores": ncpu, "kind": "oracle",
+            "sample": "one FP64 forward+adjoint at 128^3 (same model and cell size) took %.1f s; "
+                      "scaled by %dx voxels to the 256^3 step" % (dt, scale)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import fzw_inputs as fi
+    from paper_2506_03969_amd import CosmoParams, Plan, WebParams
+
+    w = fi.workload(args.workload)
+    ch = w.chains[0]
+    n = ch.n
+    print("# workload %s: %d^3, L=%g, webs=%d, regions=%d, rsd_axis=%d" % (
+        w.name, n, ch.box, w.web.n_webs, w.n_regions, w.cosmo.rsd_axis), file=sys.stderr, flush=True)
+    nu_h = fi.white_noise(ch, fi.ROLE_EVAL_NU).astype(np.float32)
+    counts_h = fi.timing_counts(ch)
+    plan = _plan(w, [ch], Plan, CosmoParams, WebParams)
+    plan.set_counts(0, torch.from_numpy(counts_h.view(np.int16)).cuda())
+    nu = torch.from_numpy(nu_h.ravel()).cuda()
+    bias = torch.from_numpy(ch.bias.astype(np.float32)[None]).cuda()
+    out = (torch.empty(1, dtype=torch.float64, device="cuda"), torch.empty_like(nu), torch.empty_like(bias))
+    for _ in range(args.warmup):
+        plan.value_and_grad(nu, bias, out)
+    torch.cuda.synchronize()
+    print("# warmup done", file=sys.stderr, flush=True)
+    gpu_s, wall = _time_steps(plan, nu, bias, out, args.steps, torch)
+    ms_per_step = 1e3 * gpu_s / args.steps
+    value = args.steps / gpu_s
+    print("# single chain: %.3f ms/step (wall %.3f ms/step)" % (ms_per_step, 1e3 * wall / args.steps),
+          file=sys.stderr, flush=True)
+
+    # per-kernel-class HIP-event timing over a second timed region
+    plan.timing(True)
+    _time_steps(plan, nu, bias, out, args.steps, torch)
+    rep = plan.timing_report()
+    plan.timing(False)
+    classes = {}
+    for k, (ms, launches, by) in rep.items():
+        if launches:
+            classes[k] = {"ms_per_step": ms / args.steps, "launches_per_step": launches / args.steps,
+                          "avg_launch_us": 1e3 * ms / launches, "GBps": by / (ms * 1e6) if ms > 0 else 0.0}
+    dom = max(rep.items(), key=lambda kv: kv[1][0])
+    dom_ms, dom_n, dom_b = dom[1]
+    achieved = dom_b / (dom_ms * 1e6)
+    total_alg = sum(v[2] for v in rep.values()) / args.steps
+    for k, v in sorted(classes.items(), key=lambda kv: -kv[1]["ms_per_step"]):
+        print("#   %-11s %7.3f ms/step %6.1f launches  %8.1f us/launch  %7.1f GB/s" % (
+            k, v["ms_per_step"], v["launches_per_step"], v["avg_launch_us"], v["GBps"]), file=sys.stderr)
+
+    # batched: several identical 256^3 chains in one plan
+    batched = None
+    if args.batch > 1:
+        del plan, out
+        torch.cuda.empty_cache()
+        chains = [ch] * args.batch
+        pb = _plan(w, chains, Plan, CosmoParams, WebParams)
+        for c in range(args.batch):
+            pb.set_counts(c, torch.from_numpy(counts_h.view(np.int16)).cuda())
+        nub = nu.repeat(args.batch)
+        biasb = bias.repeat(args.batch, 1, 1).contiguous()
+        outb = (torch.empty(args.batch, dtype=torch.float64, device="cuda"), torch.empty_like(nub),
+                torch.empty_like(biasb))
+        for _ in range(max(1, args.warmup)):
+            pb.value_and_grad(nub, biasb, outb)
+        bs = max(2, args.steps // args.batch)
+        gb, _ = _time_steps(pb, nub, biasb, outb, bs, torch)
+        batched = {"chains": args.batch, "value": args.batch * bs / gb, "unit": "grads/s",
+                   "ms_per_step": 1e3 * gb / bs}
+        print("# batched x%d: %.3f ms/step -> %.1f grads/s" % (args.batch, batched["ms_per_step"],
+                                                              batched["value"]), file=sys.stderr)
+        del pb
+        torch.cuda.empty_cache()
+
+    cpu = None if args.no_cpu else cpu_baseline(w)
+    line = {
+        "metric": "forward+adjoint logL grads/sec at 256^3 (FP32, batched vs single) + % HBM peak",
+        "value": value,
+        "unit": "grads/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %d^3 mesh, L=%g Mpc/h, %d webs, %d regions, plane-parallel RSD, "
+                               "1 chain, forward+adjoint" % (w.name, n, ch.box, w.web.n_webs, w.n_regions),
+                   "mesh": n, "box": ch.box, "chains": 1},
+        "batched": batched,
+        "algorithmic_GBps_all_kernels": total_alg / (ms_per_step * 1e6),
+        "hbm_frac_algorithmic": total_alg / (ms_per_step * 1e6) / HBM_PEAK_GBS,
+        "kernel_classes": classes,
+        "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": 1e3 * dom_ms / dom_n},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -62,7 +62,7 @@ class Cosmo:
     f_growth: float = 0.31 ** 0.55  # linear growth rate used by RSD
     r_s: float = 4.0           # ALPT Gaussian smoothing radius
     rsd_axis: int = -1         # -1: real space; 2: plane-parallel along z
-    tau_sc: float = 0.0        # smoothing of the spherical-collapse hinge (0 = exact)
+    tau_sc: float = 0.05       # width of the smooth spherical-collapse hinge (0 = exact max)
     x_floor: float = 1e-6      # floor on 1+delta inside the bias
 
 
@@ -202,6 +202,7 @@ def small_variant(w: Workload, n: int, box: Optional[float] = None) -> Workload:
 
 # ---------------------------------------------------------------- seeded draws
 ROLE_TRUTH_NU, ROLE_DATA, ROLE_EVAL_NU, ROLE_MOMENTUM, ROLE_MISC = 0, 1, 2, 3, 4
+NEAR_KAPPA = 0.05
 
 
 def rng_for(chain: Chain, role: int) -> np.random.Generator:
@@ -213,6 +214,13 @@ def white_noise(chain: Chain, role: int = ROLE_EVAL_NU, dtype=np.float64) -> np.
     g = rng_for(chain, role)
     n = chain.n
     return g.standard_normal((n, n, n)).astype(dtype)
+
+
+def near_truth_noise(chain: Chain, kappa: float = NEAR_KAPPA) -> np.ndarray:
+    """A white-noise state near the truth, sqrt(1-kappa^2) nu_truth + kappa xi,
+    standing in for a state a converged chain visits."""
+    return (np.sqrt(1.0 - kappa * kappa) * white_noise(chain, ROLE_TRUTH_NU)
+            + kappa * white_noise(chain, ROLE_EVAL_NU))
 
 
 def gamma_poisson_counts(nbar: np.ndarray, beta: np.ndarray, rng: np.random.Generator) -> np.ndarray:

@@ -1,0 +1,183 @@
+/*
+ * fzw.h: C ABI of the MI355X (gfx950) implementation of the differentiable
+ * fuzzy-cosmic-web field-level likelihood (Rossello, Kitaura et al. 2025).
+ *
+ * Problem statement (Section 2.1): a forward model M maps a white-noise field
+ * nu, bias parameters b and fixed cosmology to the expected tracer counts
+ * nbar = M_b(M_Psi(M_delta(nu)), b); the data n* enter through the
+ * negative-binomial likelihood of Section 2.7; the posterior adds a whitened
+ * Gaussian prior on nu and log-normal priors on the bias (Eq. 'posterior',
+ * Eq. 'lognormal') and is sampled with Hamiltonian Monte Carlo (Section 2.2).
+ *
+ * The stages, with the passages that define them:
+ *   M_delta : delta_L = irfftn(h(k) rfftn(nu)), h = sqrt(P(k)/dx^3)   (Appendix A)
+ *   M_Psi   : ALPT, Psi = K o Psi_2LPT + (1-K) o Psi_SC, Gaussian K of
+ *             radius r_s (Section 2.3); particles start on the mesh nodes and
+ *             are deposited with cloud-in-cell, optionally after a
+ *             plane-parallel redshift-space shift (Section 2.9)
+ *   M_b     : tidal tensors (Section 2.8, Appendix B), sorted eigenvalues,
+ *             sigmoid weights (Eq. 'sigmoid'), memberships (Eq. 'soft_cweb_p'),
+ *             per-voxel parameters interpolated over 4 or 16 regions (boxed
+ *             equation of Section 2.8), bias x^alpha exp(-(x/rho)^eps)
+ *             (Eq. 'local_bias', signed eps), normalisation sum nbar = N_tr
+ *   logL    : sum of negative-binomial log-pmfs, Gamma(beta, nbar/beta) x
+ *             Poisson (Section 2.7, Eq. 'log_likelihood'), constants included
+ *
+ * Conventions for every call:
+ *   - Pointers marked (device) are device memory owned by the caller (for
+ *     example allocated by PyTorch); the library never frees them and keeps no
+ *     reference after the call returns.  (host) pointers are read during the
+ *     call only.
+ *   - Real fields are float32, C order [x][y][z] (z fastest), one N^3 block per
+ *     chain, chains packed back to back in chain order (fzw_chain_offset).
+ *   - A bias table is float32 [n_chains][R][4] with columns
+ *     (alpha, eps, rho_th, beta_NB); R = 4 (one web) or 16 (two webs, region
+ *     4*j + k for class j of web 0 and class k of web 1); classes are ordered
+ *     void, sheet, filament, knot.
+ *   - Log-likelihoods and Hamiltonians are float64 [n_chains].
+ *   - Calls enqueue work on the plan's stream and return without waiting,
+ *     except fzw_plan_create and fzw_set_counts, which synchronise.
+ *   - A negative status means nothing was enqueued; fzw_last_error() returns a
+ *     message (thread-local, valid until the next call on the same thread).
+ *     FZW_E_HIP leaves the plan unusable: destroy it.
+ *   - Non-finite results are not errors: logL = -inf or NaN is written and the
+ *     caller's Metropolis step rejects.
+ */
+#ifndef FZW_H_
+#define FZW_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FZW_OK = 0,
+  FZW_E_ARG = -1,    /* invalid argument (null pointer, out-of-range value) */
+  FZW_E_SIZE = -2,   /* unsupported mesh size */
+  FZW_E_HIP = -3,    /* a HIP runtime call failed */
+  FZW_E_OOM = -4,    /* workspace allocation failed; the plan is not created */
+  FZW_E_STATE = -5   /* call out of order (e.g. counts not set) */
+} fzw_status;
+
+enum { FZW_WEB_PHI = 0, FZW_WEB_DELTA = 1 };
+
+/* Cosmology and gravity-solver settings, fixed for a plan (Section 2.1). */
+typedef struct {
+  double omega_m, h, sigma8, n_s; /* BBKS linear spectrum normalised to sigma8 */
+  double d1;                      /* linear growth factor at the output time */
+  double f_growth;                /* growth rate used by the RSD shift */
+  double r_s;                     /* ALPT Gaussian smoothing radius [Mpc/h] */
+  int rsd_axis;                   /* -1 real space; 0,1,2 plane-parallel line of sight */
+  double tau_sc;                  /* width of a smooth spherical-collapse hinge, 0 = exact */
+  double x_floor;                 /* floor applied to 1+delta inside the bias */
+} fzw_cosmo;
+
+/* Fuzzy cosmic-web settings (Section 2.8). */
+typedef struct {
+  int n_webs;        /* 1: Phi-web (4 regions); 2: Phi-web x delta-web (16 regions) */
+  int kind[2];       /* FZW_WEB_PHI: tensor of Phi = lap^-1 delta;
+                        FZW_WEB_DELTA: -ell^2 times the Hessian of delta */
+  double smooth_r[2];/* Gaussian smoothing radius of each web's field [Mpc/h] */
+  double ell[2];     /* scale of the delta-web tensor [Mpc/h] */
+  double steepness;  /* sigmoid steepness s */
+  double lambda_th;  /* eigenvalue threshold */
+} fzw_web;
+
+typedef struct fzw_plan fzw_plan;
+
+/* Create a plan for n_chains independent chains.  mesh_n[c] in
+ * {16,32,64,96,128,256,512}, box_l[c] > 0 (host arrays).  Chains with equal
+ * (mesh_n, box_l) that are adjacent in chain order are batched into single
+ * launches.  `stream` is a hipStream_t (NULL = default stream).  Allocates
+ * the workspace (fzw_workspace_bytes) and computes the spectral tables. */
+fzw_status fzw_plan_create(fzw_plan** out, int n_chains, const int* mesh_n, const double* box_l,
+                           const fzw_cosmo* cosmo, const fzw_web* web, void* stream);
+void fzw_plan_destroy(fzw_plan* plan);
+
+/* Copy the observed counts n* of one chain (device, uint16, N^3, C order)
+ * into the plan; also precomputes N_tr and the data-only constant
+ * sum_i lnGamma(n*_i + 1) in float64.  Synchronises. */
+fzw_status fzw_set_counts(fzw_plan* plan, int chain, const uint16_t* counts);
+
+/* Forward model and log-likelihood for every chain.
+ *   nu    (device) float32 white noise, packed chains
+ *   bias  (device) float32 [n_chains][R][4]
+ *   nbar  (device, may be NULL) float32 expected counts, packed chains
+ *   logl  (device) float64 [n_chains] */
+fzw_status fzw_forward(fzw_plan* plan, const float* nu, const float* bias, float* nbar, double* logl);
+
+/* Forward model, log-likelihood and its gradient by the hand-written adjoint.
+ *   dlogl_dnu   (device) float32, packed chains
+ *   dlogl_dbias (device) float32 [n_chains][R][4] */
+fzw_status fzw_value_and_grad(fzw_plan* plan, const float* nu, const float* bias, double* logl,
+                              float* dlogl_dnu, float* dlogl_dbias);
+
+/* Free bias parameters for HMC: n_free parameters shared by all chains.
+ * tie (host, int [R*4]) maps each table entry to a free-parameter index or -1
+ * (entry stays at its base value); a free parameter is sampled as u = ln b.
+ * prior_mu, prior_sigma (host, double [n_free]) are the log-normal
+ * hyper-parameters (Eq. 'lognormal').  n_free <= 64. */
+fzw_status fzw_set_sampling(fzw_plan* plan, const int* tie, int n_free, const double* prior_mu,
+                            const double* prior_sigma);
+
+/* One kick-drift-kick leapfrog trajectory of n_steps steps per chain, on the
+ * potential U = -logL + |nu|^2/2 + sum_f (u_f - mu_f)^2/(2 sigma_f^2), with a
+ * diagonal inverse mass matrix.  All arrays (device):
+ *   nu, p_nu, minv_nu  float32 packed chains (nu and p_nu updated in place)
+ *   u, p_u, minv_u     float32 [n_chains][n_free] (updated in place)
+ *   bias_base          float32 [n_chains][R][4] (values of the non-free entries)
+ *   step               float32 [n_chains]
+ *   h_start, h_end     float64 [n_chains]: H = U + p^T M^-1 p / 2
+ * The trajectory is captured once as a HIP graph per distinct argument set and
+ * replayed.  Accept/reject is left to the caller. */
+fzw_status fzw_leapfrog(fzw_plan* plan, float* nu, float* u, float* p_nu, float* p_u,
+                        const float* bias_base, const float* minv_nu, const float* minv_u,
+                        const float* step, int n_steps, double* h_start, double* h_end);
+
+/* Copy an intermediate field of the last forward evaluation (device
+ * destination, float32 N^3 of one chain).  Fields: 0 delta_L, 1 Psi_x,
+ * 2 Psi_y, 3 Psi_z, 4 rho (CIC density, mean 1), 5 log f (log of the
+ * unnormalised bias), 6..11 tensor of web 0 (xx,yy,zz,xy,xz,yz), 12..17 web 1.
+ * Valid until the next evaluation on the plan. */
+fzw_status fzw_get_field(fzw_plan* plan, int chain, int field, float* out);
+
+/* Standalone batched 3-D FFTs on the plan's stream (for testing and reuse).
+ * r2c: real (device) [batch][n^3] -> half spectrum (device) complex64
+ * [batch][n][n][n/2+1] (unnormalised).  c2r: the inverse, unnormalised
+ * (returns n^3 times the input field).  Uses internal scratch of the plan;
+ * n must be one of the plan's mesh sizes. */
+fzw_status fzw_fft_r2c(fzw_plan* plan, int n, int batch, const float* in, void* out_complex);
+fzw_status fzw_fft_c2r(fzw_plan* plan, int n, int batch, const void* in_complex, float* out);
+
+/* Kernel classes for per-launch timing. */
+enum {
+  FZW_K_ZPASS = 0,     /* z-axis real<->complex FFT passes */
+  FZW_K_XYPASS = 1,    /* strided x / y FFT passes with spectral multipliers */
+  FZW_K_CIC = 2,       /* cloud-in-cell deposit (sort + gather) and its adjoint */
+  FZW_K_LPT = 3,       /* 2LPT / spherical-collapse pointwise terms and adjoint */
+  FZW_K_VOXEL_FWD = 4, /* per-voxel web memberships and bias */
+  FZW_K_LIKE = 5,      /* negative-binomial likelihood pass */
+  FZW_K_VOXEL_BWD = 6, /* per-voxel adjoint of web, bias and likelihood */
+  FZW_K_COUNT = 7
+};
+/* Turn per-launch timing on (1) or off (0): every later launch of the plan's
+ * kernels (outside HIP graphs) is bracketed by HIP events on the plan's
+ * stream.  Resets the records.  Synchronises the plan's stream. */
+fzw_status fzw_timing_enable(fzw_plan* plan, int on);
+/* Sum over the recorded launches of one kernel class: elapsed milliseconds,
+ * number of launches and algorithmic bytes (each stage's distinct inputs and
+ * outputs, counted once).  (host) outputs.  Synchronises the plan's stream. */
+fzw_status fzw_timing_read(fzw_plan* plan, int klass, double* total_ms, long long* launches, double* bytes);
+
+size_t fzw_chain_offset(const fzw_plan* plan, int chain);   /* voxel offset of chain c */
+int fzw_n_regions(const fzw_plan* plan);
+size_t fzw_workspace_bytes(const fzw_plan* plan);
+const char* fzw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FZW_H_ */

@@ -1,0 +1,314 @@
+// Batched 3-D real<->complex FFT passes for gfx950.
+//
+// A real field is N^3 float in C order [x][y][z].  Its half spectrum is stored
+// [x][y][P] complex64 with P = N/2+1 rounded up to a multiple of 16 so that every
+// row starts on a 128-byte boundary; only the first N/2+1 entries of a row are
+// used.  The same layout holds after each pass: a z pass turns [x][y][z] reals
+// into [x][y][kz], a y pass [x][y][kz] into [x][ky][kz], an x pass into
+// [kx][ky][kz].  Every pass is one launch that stages a tile of lines through
+// LDS, runs a radix-2/3/4/8 Stockham FFT on all lines of the tile and writes
+// the tile back; the strided passes also apply spectral multipliers and mix
+// several inputs/outputs so that pointwise spectral work costs no extra pass.
+// Transforms are unnormalised in both directions (inverse = N^3 x).
+#include "fzw_device.hpp"
+
+namespace fzw {
+
+int spectrum_pitch(int n) { return ((n / 2 + 1) + 15) / 16 * 16; }
+
+template <int N>
+__host__ __device__ constexpr int pitch_c() { return ((N / 2 + 1) + 15) / 16 * 16; }
+
+template <int N>
+__host__ __device__ constexpr int pow2floor(int v) {
+  int p = 1;
+  while (p * 2 <= v) p *= 2;
+  return p;
+}
+// lines of the z-pass tile: a power of two with at most kTile complex values
+template <int N>
+__host__ __device__ constexpr int zlines() {
+  return pow2floor<N>(kTile / (N / 2)) > N * N ? N * N : pow2floor<N>(kTile / (N / 2));
+}
+// columns of the strided-pass tile (a power of two; columns past N/2 are masked)
+template <int N>
+__host__ __device__ constexpr int xycols() {
+  return pow2floor<N>(kTile / N) > 256 ? 256 : pow2floor<N>(kTile / N);
+}
+
+struct ZArgs {
+  const void* in[16];
+  void* out[16];
+  int narr;
+  long long in_chain_stride, out_chain_stride;   // in elements of the array type
+};
+
+// --------------------------------------------------------------- z: R2C
+template <int N>
+__global__ __launch_bounds__(kThreads) void zpass_r2c_kernel(ZArgs a, const float2* __restrict__ tw_half,
+                                                             const float2* __restrict__ tw_full) {
+  constexpr int M = N / 2;
+  constexpr int L = zlines<N>();
+  constexpr int P = pitch_c<N>();
+  __shared__ float2 lds[L * M];
+  __shared__ float2 twh[M];
+  __shared__ float2 twf[N];
+  const int t = threadIdx.x;
+  const int arr = blockIdx.z % a.narr;
+  const long long chain = blockIdx.z / a.narr;
+  const float2* in = reinterpret_cast<const float2*>(a.in[arr]) + chain * (a.in_chain_stride / 2);
+  float2* out = reinterpret_cast<float2*>(a.out[arr]) + chain * a.out_chain_stride;
+  const long long line0 = (long long)blockIdx.x * L;
+  for (int i = t; i < M; i += kThreads) twh[i] = tw_half[i];
+  for (int i = t; i < N; i += kThreads) twf[i] = tw_full[i];
+  const float2* src = in + line0 * M;
+  for (int e = t; e < L * M; e += kThreads) lds[e] = src[e];
+  __syncthreads();
+  fft_lines<M, L, M, false>(lds, twh);
+  for (int e = t; e < L * (M + 1); e += kThreads) {
+    const int line = e / (M + 1);
+    const int k = e - line * (M + 1);
+    const float2 zk = lds[line * M + (k == M ? 0 : k)];
+    const float2 zm = lds[line * M + (k == 0 ? 0 : M - k)];
+    const float2 A = cadd(zk, cconj(zm));
+    const float2 B = csub(zk, cconj(zm));
+    const float2 wB = cmul(twf[k], B);
+    out[(line0 + line) * P + k] = make_float2(0.5f * (A.x + wB.y), 0.5f * (A.y - wB.x));
+  }
+}
+
+// --------------------------------------------------------------- z: C2R
+template <int N>
+__global__ __launch_bounds__(kThreads) void zpass_c2r_kernel(ZArgs a, const float2* __restrict__ tw_half,
+                                                             const float2* __restrict__ tw_full) {
+  constexpr int M = N / 2;
+  constexpr int L = zlines<N>();
+  constexpr int P = pitch_c<N>();
+  __shared__ float2 lds[L * M];
+  __shared__ float2 twh[M];
+  __shared__ float2 twf[N];
+  const int t = threadIdx.x;
+  const int arr = blockIdx.z % a.narr;
+  const long long chain = blockIdx.z / a.narr;
+  const float2* in = reinterpret_cast<const float2*>(a.in[arr]) + chain * a.in_chain_stride;
+  float2* out = reinterpret_cast<float2*>(a.out[arr]) + chain * (a.out_chain_stride / 2);
+  const long long line0 = (long long)blockIdx.x * L;
+  for (int i = t; i < M; i += kThreads) twh[i] = tw_half[i];
+  for (int i = t; i < N; i += kThreads) twf[i] = tw_full[i];
+  __syncthreads();
+  for (int e = t; e < L * M; e += kThreads) {
+    const int line = e / M;
+    const int k = e - line * M;
+    const float2* row = in + (line0 + line) * P;
+    float2 xk = row[k];
+    float2 xm = row[M - k];
+    if (k == 0) {
+      xk.y = 0.f;
+      xm.y = 0.f;
+    }
+    const float2 A = cadd(xk, cconj(xm));
+    const float2 B = csub(xk, cconj(xm));
+    const float2 cB = cmul(cconj(twf[k]), B);
+    lds[e] = make_float2(A.x - cB.y, A.y + cB.x);
+  }
+  __syncthreads();
+  fft_lines<M, L, M, true>(lds, twh);
+  float2* dst = out + line0 * M;
+  for (int e = t; e < L * M; e += kThreads) dst[e] = lds[e];
+}
+
+// ------------------------------------------------------- strided x / y pass
+// Tile: all N rows (the transform axis) x C consecutive kz columns.  Thread t
+// owns column t % C and rows t / C + j * (NT / C), so its wave vector along z
+// and along the batch axis is fixed and only the row index varies.
+constexpr int kThreadsXY = 512;
+
+template <int N, int AXIS, int NMID>
+__global__ __launch_bounds__(kThreadsXY) void xy_pass_kernel(PassArgs a, const float2* __restrict__ twg) {
+  constexpr int NT = kThreadsXY;
+  constexpr int M = N / 2;
+  constexpr int P = pitch_c<N>();
+  constexpr int C = xycols<N>();
+  constexpr int LS = N + 1;
+  constexpr int RS = NT / C;          // rows per sweep
+  constexpr int E = N / RS;           // elements per thread
+  static_assert(NT % C == 0 && N % RS == 0, "tile shape");
+  __shared__ float2 lds[C * LS];
+  __shared__ float2 tw[N];
+  const int t = threadIdx.x;
+  const int c = t % C;
+  const int r0 = t / C;
+  const int c0 = blockIdx.x * C;
+  const int b = blockIdx.y;
+  const long long chain = blockIdx.z;
+  const long long rstride = AXIS == 0 ? (long long)N * P : (long long)P;
+  const bool valid = (c0 + c) <= M;
+  const long long base = chain * a.chain_stride + (AXIS == 0 ? (long long)b * P : (long long)b * N * P) + c0 + c;
+  for (int i = t; i < N; i += NT) tw[i] = twg[i];
+  const int nb = freq_index(b, N);
+  // masked columns (past N/2) take kz = 0 so that table lookups stay in range
+  const int nz = valid ? c0 + c : 0;
+  const int nyq = N / 2;
+  float2* lcol = lds + c * LS;
+
+  float2 mid[NMID][E];
+#pragma unroll
+  for (int m = 0; m < NMID; ++m)
+#pragma unroll
+    for (int j = 0; j < E; ++j) mid[m][j] = make_float2(0.f, 0.f);
+
+  __syncthreads();
+  for (int i = 0; i < a.nin; ++i) {
+    const float2* src = a.in[i] + base;
+    float2 val[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int r = r0 + j * RS;
+      val[j] = valid ? src[r * rstride] : make_float2(0.f, 0.f);
+    }
+    if (a.in_fft & (1u << i)) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) lcol[r0 + j * RS] = val[j];
+      __syncthreads();
+      fft_lines<N, C, LS, false, NT>(lds, tw);
+#pragma unroll
+      for (int j = 0; j < E; ++j) val[j] = lcol[r0 + j * RS];
+      __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < NMID; ++m) {
+      {
+        const SpecOp op = a.A[m][i];
+        if (op.re != 0.f || op.im != 0.f) {
+#pragma unroll
+          for (int j = 0; j < E; ++j) {
+            KVec kv;
+            const int nr = freq_index(r0 + j * RS, N);
+            kv.n[0] = AXIS == 0 ? nr : 0;
+            kv.n[1] = AXIS == 0 ? nb : nr;
+            kv.n[2] = nz;
+            kv.n2 = kv.n[0] * kv.n[0] + kv.n[1] * kv.n[1] + nz * nz;
+            const float2 w = spec_eval(op, kv, a.kf, nyq, a.tabs, a.tab_stride);
+            mid[m][j] = cadd(mid[m][j], cmul(w, val[j]));
+          }
+        }
+      }
+    }
+  }
+
+  for (int o = 0; o < a.nout; ++o) {
+    float2 val[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) val[j] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int m = 0; m < NMID; ++m) {
+      {
+        const SpecOp op = a.B[o][m];
+        if (op.re != 0.f || op.im != 0.f) {
+#pragma unroll
+          for (int j = 0; j < E; ++j) {
+            KVec kv;
+            const int nr = freq_index(r0 + j * RS, N);
+            kv.n[0] = AXIS == 0 ? nr : 0;
+            kv.n[1] = AXIS == 0 ? nb : nr;
+            kv.n[2] = nz;
+            kv.n2 = kv.n[0] * kv.n[0] + kv.n[1] * kv.n[1] + nz * nz;
+            const float2 w = spec_eval(op, kv, a.kf, nyq, a.tabs, a.tab_stride);
+            val[j] = cadd(val[j], cmul(w, mid[m][j]));
+          }
+        }
+      }
+    }
+    if (a.out_fft & (1u << o)) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) lcol[r0 + j * RS] = val[j];
+      __syncthreads();
+      fft_lines<N, C, LS, true, NT>(lds, tw);
+#pragma unroll
+      for (int j = 0; j < E; ++j) val[j] = lcol[r0 + j * RS];
+      __syncthreads();
+    }
+    if (valid) {
+      float2* dst = a.out[o] + base;
+#pragma unroll
+      for (int j = 0; j < E; ++j) dst[(r0 + j * RS) * rstride] = val[j];
+    }
+  }
+}
+
+// ------------------------------------------------------------- launchers
+template <int N>
+static void zr2c(const ZArgs& za, long long chains, const float2* twh, const float2* twf, hipStream_t s) {
+  constexpr int L = zlines<N>();
+  dim3 grid((N * N) / L, 1, (unsigned)(za.narr * chains));
+  hipLaunchKernelGGL(zpass_r2c_kernel<N>, grid, dim3(kThreads), 0, s, za, twh, twf);
+}
+template <int N>
+static void zc2r(const ZArgs& za, long long chains, const float2* twh, const float2* twf, hipStream_t s) {
+  constexpr int L = zlines<N>();
+  dim3 grid((N * N) / L, 1, (unsigned)(za.narr * chains));
+  hipLaunchKernelGGL(zpass_c2r_kernel<N>, grid, dim3(kThreads), 0, s, za, twh, twf);
+}
+
+#define FZW_DISPATCH_N(n, F, ...)                 \
+  switch (n) {                                    \
+    case 16: F<16>(__VA_ARGS__); break;           \
+    case 32: F<32>(__VA_ARGS__); break;           \
+    case 64: F<64>(__VA_ARGS__); break;           \
+    case 96: F<96>(__VA_ARGS__); break;           \
+    case 128: F<128>(__VA_ARGS__); break;         \
+    case 256: F<256>(__VA_ARGS__); break;         \
+    case 512: F<512>(__VA_ARGS__); break;         \
+    default: break;                               \
+  }
+
+void launch_zpass_r2c(int n, const float* const* in, float2* const* out, int narr, long long chains,
+                      long long in_chain_stride, long long out_chain_stride, const float2* tw_half,
+                      const float2* tw_full, hipStream_t s) {
+  ZArgs za{};
+  for (int i = 0; i < narr; ++i) {
+    za.in[i] = in[i];
+    za.out[i] = out[i];
+  }
+  za.narr = narr;
+  za.in_chain_stride = in_chain_stride;
+  za.out_chain_stride = out_chain_stride;
+  FZW_DISPATCH_N(n, zr2c, za, chains, tw_half, tw_full, s);
+}
+
+void launch_zpass_c2r(int n, const float2* const* in, float* const* out, int narr, long long chains,
+                      long long in_chain_stride, long long out_chain_stride, const float2* tw_half,
+                      const float2* tw_full, hipStream_t s) {
+  ZArgs za{};
+  for (int i = 0; i < narr; ++i) {
+    za.in[i] = in[i];
+    za.out[i] = out[i];
+  }
+  za.narr = narr;
+  za.in_chain_stride = in_chain_stride;
+  za.out_chain_stride = out_chain_stride;
+  FZW_DISPATCH_N(n, zc2r, za, chains, tw_half, tw_full, s);
+}
+
+template <int N>
+static void xyp(int axis, const PassArgs& a, int chains, const float2* tw, hipStream_t s) {
+  constexpr int C = xycols<N>();
+  dim3 grid((N / 2 + 1 + C - 1) / C, N, chains);
+#define FZW_XY(AX, NM) hipLaunchKernelGGL((xy_pass_kernel<N, AX, NM>), grid, dim3(kThreadsXY), 0, s, a, tw)
+  if (axis == 0) {
+    if (a.nmid == 1) FZW_XY(0, 1);
+    else if (a.nmid == 2) FZW_XY(0, 2);
+    else FZW_XY(0, 3);
+  } else {
+    if (a.nmid == 1) FZW_XY(1, 1);
+    else if (a.nmid == 2) FZW_XY(1, 2);
+    else FZW_XY(1, 3);
+  }
+#undef FZW_XY
+}
+
+void launch_xy_pass(int n, int axis, const PassArgs& a, int chains, const float2* tw, hipStream_t s) {
+  FZW_DISPATCH_N(n, xyp, axis, a, chains, tw, s);
+}
+
+}  // namespace fzw

@@ -1,0 +1,59 @@
+// Internal interfaces between the host runtime and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fzw {
+
+// A spectral multiplier m(k) = (re + i im) * K(ax0, ax1) * tab0[|n|^2] * tab1[|n|^2]
+// where K is 1 (no axis), k_a (one axis, zero on that axis' Nyquist index),
+// k_a k_b (a != b, each zeroed on its Nyquist index) or k_a^2 (a == b).
+struct SpecOp {
+  float re, im;
+  signed char ax[2];
+  signed char tb[2];
+};
+
+inline SpecOp spec_zero() { return SpecOp{0.f, 0.f, {-1, -1}, {-1, -1}}; }
+inline SpecOp spec_const(float re, float im = 0.f) { return SpecOp{re, im, {-1, -1}, {-1, -1}}; }
+inline SpecOp spec(float re, float im, int a0, int a1, int t0, int t1) {
+  return SpecOp{re, im, {(signed char)a0, (signed char)a1}, {(signed char)t0, (signed char)t1}};
+}
+inline bool spec_is_zero(const SpecOp& s) { return s.re == 0.f && s.im == 0.f; }
+
+constexpr int kMaxIn = 8;
+constexpr int kMaxMid = 3;
+constexpr int kMaxOut = 6;
+
+// One strided (x or y) pass over a half spectrum stored [x][y][P] complex.
+// Phase 1: each input is transformed forward along the axis (if its bit in
+// `in_fft` is set) and mixed: mid[m] = sum_i A[m][i] X_i.
+// Phase 2: out[o] = B[o] . mid, inverse-transformed along the axis if its bit
+// in `out_fft` is set, then stored.
+struct PassArgs {
+  const float2* in[kMaxIn];
+  float2* out[kMaxOut];
+  int nin, nmid, nout;
+  unsigned in_fft, out_fft;
+  SpecOp A[kMaxMid][kMaxIn];
+  SpecOp B[kMaxOut][kMaxMid];
+  long long chain_stride;     // elements between chains batched on grid.z
+  const float* tabs;          // radial tables [ntab][tab_stride]
+  int tab_stride;
+  float kf;                   // 2 pi / L
+};
+
+// Launchers (defined next to their kernels).
+void launch_zpass_r2c(int n, const float* const* in, float2* const* out, int narr, long long chains,
+                      long long in_chain_stride, long long out_chain_stride, const float2* tw_half,
+                      const float2* tw_full, hipStream_t s);
+void launch_zpass_c2r(int n, const float2* const* in, float* const* out, int narr, long long chains,
+                      long long in_chain_stride, long long out_chain_stride, const float2* tw_half,
+                      const float2* tw_full, hipStream_t s);
+// axis 0 = x pass, 1 = y pass
+void launch_xy_pass(int n, int axis, const PassArgs& a, int chains, const float2* tw, hipStream_t s);
+
+int spectrum_pitch(int n);    // P: padded length of a row of N/2+1 modes
+
+}  // namespace fzw

@@ -1,0 +1,866 @@
+// Non-FFT kernels of the forward model and its adjoint for gfx950: LPT
+// pointwise terms, cloud-in-cell deposit by counting sort with a gather, its
+// gather adjoint, the fused per-voxel web/bias kernels, the likelihood pass,
+// fixed-order FP64 reductions and the leapfrog updates.
+#include "fzw_device.hpp"
+#include "fzw_ops.hpp"
+
+namespace fzw {
+
+static inline unsigned grid_for(long long n, int threads, unsigned cap = 1u << 20) {
+  long long g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+// ------------------------------------------------------------------- fill
+__global__ void fill_i32_kernel(int* p, long long n, int v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void fill_f32_kernel(float* p, long long n, float v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+void launch_fill_i32(int* p, long long n, int v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, p, n, v);
+}
+void launch_fill_f32(float* p, long long n, float v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, p, n, v);
+}
+
+// ------------------------------------------------------------ LPT pointwise
+__device__ __forceinline__ void sc_hinge(float a, float tau, float& hv, float& hd) {
+  if (tau > 0.f) {
+    const float r = sqrtf(a * a + tau * tau);
+    hv = 0.5f * (a + r);
+    hd = 0.5f * (1.f + a / r);
+  } else {
+    hv = a > 0.f ? a : 0.f;
+    hd = a > 0.f ? 1.f : 0.f;
+  }
+}
+
+// 2LPT source S2 = sum_{i<j} (phi_ii phi_jj - phi_ij^2) and the spherical
+// collapse divergence 3 (sqrt(hinge(1 - 2 D1 delta_L / 3)) - 1), delta_L = tr phi.
+__global__ void lpt_fwd_kernel(LptArgs a) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.n; i += (long long)gridDim.x * blockDim.x) {
+    const float xx = a.phi[0][i], yy = a.phi[1][i], zz = a.phi[2][i];
+    const float xy = a.phi[3][i], xz = a.phi[4][i], yz = a.phi[5][i];
+    const float dl = xx + yy + zz;
+    a.s2[i] = xx * yy + xx * zz + yy * zz - xy * xy - xz * xz - yz * yz;
+    float hv, hd;
+    sc_hinge(1.f - (2.f / 3.f) * a.d1 * dl, a.tau, hv, hd);
+    a.dsc[i] = 3.f * (sqrtf(hv) - 1.f);
+  }
+}
+
+// Adjoint of lpt_fwd: phi cotangents from the S2 and d_SC cotangents (written
+// in place over the phi cotangent buffers, which may alias phi).
+__global__ void lpt_bwd_kernel(LptArgs a) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.n; i += (long long)gridDim.x * blockDim.x) {
+    const float xx = a.phi[0][i], yy = a.phi[1][i], zz = a.phi[2][i];
+    const float xy = a.phi[3][i], xz = a.phi[4][i], yz = a.phi[5][i];
+    const float g2 = a.s2[i];
+    const float gs = a.dsc[i];
+    float hv, hd;
+    sc_hinge(1.f - (2.f / 3.f) * a.d1 * (xx + yy + zz), a.tau, hv, hd);
+    const float gdl = hv > 0.f ? -gs * a.d1 * hd * rsqrtf(hv) : 0.f;
+    a.dphi[0][i] = g2 * (yy + zz) + gdl;
+    a.dphi[1][i] = g2 * (xx + zz) + gdl;
+    a.dphi[2][i] = g2 * (xx + yy) + gdl;
+    a.dphi[3][i] = -2.f * g2 * xy;
+    a.dphi[4][i] = -2.f * g2 * xz;
+    a.dphi[5][i] = -2.f * g2 * yz;
+  }
+}
+
+void launch_lpt_fwd(const LptArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(lpt_fwd_kernel, dim3(grid_for(a.n, 256, 16384)), dim3(256), 0, s, a);
+}
+void launch_lpt_bwd(const LptArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(lpt_bwd_kernel, dim3(grid_for(a.n, 256, 16384)), dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------------- CIC
+// Cell of a particle: lattice node + floor(Psi * scale); the fractional part
+// is formed from the displacement alone, never from absolute coordinates.
+__device__ __forceinline__ void cic_locate(const CicArgs& a, long long p, int n, int& cx, int& cy, int& cz,
+                                           float& tx, float& ty, float& tz) {
+  const int ix = (int)(p / ((long long)n * n));
+  const int iy = (int)((p / n) % n);
+  const int iz = (int)(p % n);
+  const float dx = a.psi[0][p] * a.scale[0];
+  const float dy = a.psi[1][p] * a.scale[1];
+  const float dz = a.psi[2][p] * a.scale[2];
+  const float fx = floorf(dx), fy = floorf(dy), fz = floorf(dz);
+  tx = dx - fx;
+  ty = dy - fy;
+  tz = dz - fz;
+  cx = (ix + (int)fx) % n;
+  cy = (iy + (int)fy) % n;
+  cz = (iz + (int)fz) % n;
+  cx += cx < 0 ? n : 0;
+  cy += cy < 0 ? n : 0;
+  cz += cz < 0 ? n : 0;
+}
+
+// Key of every particle and its slot inside the bucket (integer atomics only).
+__global__ void cic_count_kernel(CicArgs a) {
+  const long long nv = a.nv;
+  const int n = a.n;
+  const long long c = blockIdx.y;
+  CicArgs b = a;
+  for (int d = 0; d < 3; ++d) b.psi[d] = a.psi[d] + c * nv;
+  int* count = a.count + c * nv;
+  int2* ks = a.keyslot + c * nv;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nv; p += (long long)gridDim.x * blockDim.x) {
+    int cx, cy, cz;
+    float tx, ty, tz;
+    cic_locate(b, p, n, cx, cy, cz, tx, ty, tz);
+    const int key = (cx * n + cy) * n + cz;
+    const int slot = atomicAdd(count + key, 1);
+    ks[p] = make_int2(key, slot);
+  }
+}
+
+// Exclusive scan of the bucket counts: per-block totals, a single-block scan
+// of the totals, then per-block local scans.
+constexpr int kScanBlock = 4096;
+__global__ void scan_reduce_kernel(const int* __restrict__ count, long long nv, int* __restrict__ bsum, int nb) {
+  __shared__ int red[256];
+  const long long c = blockIdx.y;
+  const int* cnt = count + c * nv;
+  const long long base = (long long)blockIdx.x * kScanBlock;
+  int s = 0;
+  for (int i = threadIdx.x; i < kScanBlock; i += 256) {
+    const long long g = base + i;
+    if (g < nv) s += cnt[g];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[c * nb + blockIdx.x] = red[0];
+}
+
+__global__ void scan_blocks_kernel(int* bsum, int nb) {
+  // one workgroup of 1024 threads per chain, exclusive scan in place
+  __shared__ int tot[1024];
+  const long long c = blockIdx.x;
+  int* b = bsum + c * nb;
+  const int per = (nb + 1023) / 1024;
+  const int lo = threadIdx.x * per;
+  int s = 0;
+  for (int i = 0; i < per; ++i)
+    if (lo + i < nb) s += b[lo + i];
+  tot[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = threadIdx.x >= off ? tot[threadIdx.x - off] : 0;
+    __syncthreads();
+    tot[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = threadIdx.x > 0 ? tot[threadIdx.x - 1] : 0;
+  for (int i = 0; i < per; ++i) {
+    if (lo + i < nb) {
+      const int v = b[lo + i];
+      b[lo + i] = run;
+      run += v;
+    }
+  }
+}
+
+__global__ void scan_down_kernel(const int* __restrict__ count, long long nv, const int* __restrict__ bsum, int nb,
+                                 int* __restrict__ offset) {
+  __shared__ int part[256];
+  const long long c = blockIdx.y;
+  const int* cnt = count + c * nv;
+  int* off = offset + c * (nv + 1);
+  const long long base = (long long)blockIdx.x * kScanBlock;
+  constexpr int PER = kScanBlock / 256;
+  int v[PER];
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const long long g = base + threadIdx.x * PER + i;
+    v[i] = g < nv ? cnt[g] : 0;
+    s += v[i];
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const int x = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += x;
+    __syncthreads();
+  }
+  int run = bsum[c * nb + blockIdx.x] + (threadIdx.x > 0 ? part[threadIdx.x - 1] : 0);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const long long g = base + threadIdx.x * PER + i;
+    if (g < nv) off[g] = run;
+    run += v[i];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) off[nv] = run;
+}
+
+// Scatter the fractional offsets into bucket order.
+__global__ void cic_scatter_kernel(CicArgs a) {
+  const long long nv = a.nv;
+  const int n = a.n;
+  const long long c = blockIdx.y;
+  CicArgs b = a;
+  for (int d = 0; d < 3; ++d) b.psi[d] = a.psi[d] + c * nv;
+  const int2* ks = a.keyslot + c * nv;
+  const int* off = a.offset + c * (nv + 1);
+  float4* sorted = a.sorted + c * nv;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nv; p += (long long)gridDim.x * blockDim.x) {
+    int cx, cy, cz;
+    float tx, ty, tz;
+    cic_locate(b, p, n, cx, cy, cz, tx, ty, tz);
+    const int2 k = ks[p];
+    sorted[off[k.x] + k.y] = make_float4(tx, ty, tz, 0.f);
+  }
+}
+
+// Gather deposit: every node sums the trilinear weights of the particles in
+// the 8 buckets that touch it.  The sum is accumulated in 64-bit fixed point
+// (2^-32 resolution), so it does not depend on the order of particles inside
+// a bucket: the result is bitwise reproducible.
+__global__ void cic_gather_kernel(CicArgs a) {
+  const long long nv = a.nv;
+  const int n = a.n;
+  const long long c = blockIdx.y;
+  const int* off = a.offset + c * (nv + 1);
+  const float4* sorted = a.sorted + c * nv;
+  float* rho = a.rho + c * nv;
+  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nv; q += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(q / ((long long)n * n));
+    const int y = (int)((q / n) % n);
+    const int z = (int)(q % n);
+    long long acc = 0;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
+      const int bx = ox ? (x == 0 ? n - 1 : x - 1) : x;
+      const int by = oy ? (y == 0 ? n - 1 : y - 1) : y;
+      const int bz = oz ? (z == 0 ? n - 1 : z - 1) : z;
+      const int key = (bx * n + by) * n + bz;
+      const int lo = off[key], hi = off[key + 1];
+      for (int s = lo; s < hi; ++s) {
+        const float4 t = sorted[s];
+        const float w = (ox ? t.x : 1.f - t.x) * (oy ? t.y : 1.f - t.y) * (oz ? t.z : 1.f - t.z);
+        acc += __float2ll_rn(w * 4294967296.0f);
+      }
+    }
+    rho[q] = (float)((double)acc * (1.0 / 4294967296.0));
+  }
+}
+
+// Adjoint: each particle gathers the density cotangent at its 8 nodes and
+// writes the displacement cotangent (may alias the displacement buffers).
+__global__ void cic_adjoint_kernel(CicArgs a) {
+  const long long nv = a.nv;
+  const int n = a.n;
+  const long long c = blockIdx.y;
+  CicArgs b = a;
+  for (int d = 0; d < 3; ++d) b.psi[d] = a.psi[d] + c * nv;
+  const float* g = a.drho + c * nv;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nv; p += (long long)gridDim.x * blockDim.x) {
+    int cx, cy, cz;
+    float tx, ty, tz;
+    cic_locate(b, p, n, cx, cy, cz, tx, ty, tz);
+    const int nx = cx + 1 == n ? 0 : cx + 1;
+    const int ny = cy + 1 == n ? 0 : cy + 1;
+    const int nz = cz + 1 == n ? 0 : cz + 1;
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
+      const float v = g[((ox ? nx : cx) * n + (oy ? ny : cy)) * (long long)n + (oz ? nz : cz)];
+      const float wx = ox ? tx : 1.f - tx, wy = oy ? ty : 1.f - ty, wz = oz ? tz : 1.f - tz;
+      const float sx = ox ? 1.f : -1.f, sy = oy ? 1.f : -1.f, sz = oz ? 1.f : -1.f;
+      gx += v * sx * wy * wz;
+      gy += v * wx * sy * wz;
+      gz += v * wx * wy * sz;
+    }
+    a.dpsi[0][c * nv + p] = gx * a.scale[0];
+    a.dpsi[1][c * nv + p] = gy * a.scale[1];
+    a.dpsi[2][c * nv + p] = gz * a.scale[2];
+  }
+}
+
+void launch_cic_deposit(const CicArgs& a, int chains, hipStream_t s) {
+  const long long nv = a.nv;
+  launch_fill_i32(a.count, nv * chains, 0, s);
+  dim3 gp(grid_for(nv, 256, 32768), chains);
+  hipLaunchKernelGGL(cic_count_kernel, gp, dim3(256), 0, s, a);
+  const int nb = (int)((nv + kScanBlock - 1) / kScanBlock);
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb, chains), dim3(256), 0, s, a.count, nv, a.bsum, nb);
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(chains), dim3(1024), 0, s, a.bsum, nb);
+  hipLaunchKernelGGL(scan_down_kernel, dim3(nb, chains), dim3(256), 0, s, a.count, nv, a.bsum, nb, a.offset);
+  hipLaunchKernelGGL(cic_scatter_kernel, gp, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(cic_gather_kernel, gp, dim3(256), 0, s, a);
+}
+
+void launch_cic_adjoint(const CicArgs& a, int chains, hipStream_t s) {
+  dim3 gp(grid_for(a.nv, 256, 32768), chains);
+  hipLaunchKernelGGL(cic_adjoint_kernel, gp, dim3(256), 0, s, a);
+}
+
+// ------------------------------------------------------- symmetric 3x3 eigen
+// Eigenvalues of a symmetric 3x3 tensor, descending, by the trigonometric
+// solution of the characteristic cubic (Smith 1961).
+__device__ __forceinline__ void eig3_values(const float t[6], float lam[3], float& q, float& p) {
+  q = (t[0] + t[1] + t[2]) * (1.f / 3.f);
+  const float a = t[0] - q, b = t[1] - q, c = t[2] - q;
+  const float p2 = (a * a + b * b + c * c + 2.f * (t[3] * t[3] + t[4] * t[4] + t[5] * t[5])) * (1.f / 6.f);
+  if (!(p2 > 0.f)) {
+    lam[0] = lam[1] = lam[2] = q;
+    p = 0.f;
+    return;
+  }
+  p = sqrtf(p2);
+  const float ip = 1.f / p;
+  const float ba = a * ip, bb = b * ip, bc = c * ip, bxy = t[3] * ip, bxz = t[4] * ip, byz = t[5] * ip;
+  const float det = ba * (bb * bc - byz * byz) - bxy * (bxy * bc - byz * bxz) + bxz * (bxy * byz - bb * bxz);
+  float r = 0.5f * det;
+  r = fminf(1.f, fmaxf(-1.f, r));
+  const float phi = acosf(r) * (1.f / 3.f);
+  lam[0] = q + 2.f * p * cosf(phi);
+  lam[2] = q + 2.f * p * cosf(phi + 2.0943951023931954923f);
+  lam[1] = 3.f * q - lam[0] - lam[2];
+}
+
+__device__ __forceinline__ void cross3(const float* a, const float* b, float* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Unit eigenvector of eigenvalue l from the largest cross product of two rows
+// of T - l I; returns false when T - l I has rank < 2 numerically.
+__device__ __forceinline__ bool eig3_vector(const float t[6], float l, float scale4, float v[3]) {
+  const float r0[3] = {t[0] - l, t[3], t[4]};
+  const float r1[3] = {t[3], t[1] - l, t[5]};
+  const float r2[3] = {t[4], t[5], t[2] - l};
+  float c0[3], c1[3], c2[3];
+  cross3(r0, r1, c0);
+  cross3(r0, r2, c1);
+  cross3(r1, r2, c2);
+  const float n0 = c0[0] * c0[0] + c0[1] * c0[1] + c0[2] * c0[2];
+  const float n1 = c1[0] * c1[0] + c1[1] * c1[1] + c1[2] * c1[2];
+  const float n2 = c2[0] * c2[0] + c2[1] * c2[1] + c2[2] * c2[2];
+  const float* best = c0;
+  float nb = n0;
+  if (n1 > nb) { best = c1; nb = n1; }
+  if (n2 > nb) { best = c2; nb = n2; }
+  if (!(nb > 1e-24f * scale4)) return false;
+  const float s = rsqrtf(nb);
+  v[0] = best[0] * s;
+  v[1] = best[1] * s;
+  v[2] = best[2] * s;
+  return true;
+}
+
+__device__ __forceinline__ void any_orthogonal(const float* a, float* v) {
+  // unit vector orthogonal to unit a
+  float e[3] = {0.f, 0.f, 0.f};
+  const float ax = fabsf(a[0]), ay = fabsf(a[1]), az = fabsf(a[2]);
+  if (ax <= ay && ax <= az) e[0] = 1.f;
+  else if (ay <= az) e[1] = 1.f;
+  else e[2] = 1.f;
+  float c[3];
+  cross3(a, e, c);
+  const float s = rsqrtf(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+  v[0] = c[0] * s;
+  v[1] = c[1] * s;
+  v[2] = c[2] * s;
+}
+
+// Gradient of a function of the eigenvalues with respect to the tensor:
+// G = sum_n g_n v_n v_n^T = g2 I + (g1 - g2) v1 v1^T + (g3 - g2) v3 v3^T.
+// Returned as cotangents of the 6 stored components (off-diagonals doubled).
+__device__ __forceinline__ void eig3_grad(const float t[6], const float lam[3], float p, const float g[3],
+                                          float out[6]) {
+  float v1[3] = {1.f, 0.f, 0.f}, v3[3] = {0.f, 0.f, 1.f};
+  if (p > 0.f) {
+    const float scale4 = (p * p) * (p * p) * 81.f;
+    const bool first_top = (lam[0] - lam[1]) >= (lam[1] - lam[2]);
+    float* va = first_top ? v1 : v3;
+    float* vb = first_top ? v3 : v1;
+    const float la = first_top ? lam[0] : lam[2];
+    const float lb = first_top ? lam[2] : lam[0];
+    float tmp[3];
+    if (eig3_vector(t, la, scale4, tmp)) {
+      va[0] = tmp[0]; va[1] = tmp[1]; va[2] = tmp[2];
+    } else {
+      va[0] = first_top ? 1.f : 0.f; va[1] = 0.f; va[2] = first_top ? 0.f : 1.f;
+    }
+    bool okb = eig3_vector(t, lb, scale4, tmp);
+    if (okb) {
+      const float d = tmp[0] * va[0] + tmp[1] * va[1] + tmp[2] * va[2];
+      tmp[0] -= d * va[0];
+      tmp[1] -= d * va[1];
+      tmp[2] -= d * va[2];
+      const float nn = tmp[0] * tmp[0] + tmp[1] * tmp[1] + tmp[2] * tmp[2];
+      okb = nn > 1e-12f;
+      if (okb) {
+        const float s = rsqrtf(nn);
+        vb[0] = tmp[0] * s; vb[1] = tmp[1] * s; vb[2] = tmp[2] * s;
+      }
+    }
+    if (!okb) any_orthogonal(va, vb);
+  }
+  const float a1 = g[0] - g[1], a3 = g[2] - g[1];
+  out[0] = g[1] + a1 * v1[0] * v1[0] + a3 * v3[0] * v3[0];
+  out[1] = g[1] + a1 * v1[1] * v1[1] + a3 * v3[1] * v3[1];
+  out[2] = g[1] + a1 * v1[2] * v1[2] + a3 * v3[2] * v3[2];
+  out[3] = 2.f * (a1 * v1[0] * v1[1] + a3 * v3[0] * v3[1]);
+  out[4] = 2.f * (a1 * v1[0] * v1[2] + a3 * v3[0] * v3[2]);
+  out[5] = 2.f * (a1 * v1[1] * v1[2] + a3 * v3[1] * v3[2]);
+}
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.f / (1.f + expf(-x)); }
+
+// Sigmoid weights and memberships of one web (V, S, F, K).
+__device__ __forceinline__ void web_memberships(const float lam[3], float s, float th, float w[3], float pm[4]) {
+#pragma unroll
+  for (int n = 0; n < 3; ++n) w[n] = sigmoidf(s * (lam[n] - th));
+  pm[0] = 1.f - w[0];
+  pm[1] = w[0] - w[1];
+  pm[2] = w[1] - w[2];
+  pm[3] = w[2];
+}
+
+// ------------------------------------------------ NB constants per voxel
+// sum_{m<n} ln(beta+m) = lnGamma(n+beta) - lnGamma(beta), and its beta
+// derivative sum_{m<n} 1/(beta+m).
+__device__ __forceinline__ double digamma_d(double x) {
+  // recurrence up to x >= 8, then the asymptotic series (Abramowitz & Stegun 6.3.18)
+  double r = 0.0;
+  while (x < 8.0) {
+    r -= 1.0 / x;
+    x += 1.0;
+  }
+  const double ix = 1.0 / x, ix2 = ix * ix;
+  return r + log(x) - 0.5 * ix -
+         ix2 * (1.0 / 12 - ix2 * (1.0 / 120 - ix2 * (1.0 / 252 - ix2 * (1.0 / 240 - ix2 * (1.0 / 132)))));
+}
+
+// sum_{m<n} ln(beta+m) = lnGamma(n+beta) - lnGamma(beta) and its beta
+// derivative sum_{m<n} 1/(beta+m), in float64: counts above 64 are rare and
+// take the special functions out of line.
+__device__ __noinline__ void nb_gamma_big(int n, double beta, double& lg, double& dg) {
+  lg = lgamma((double)n + beta) - lgamma(beta);
+  dg = digamma_d((double)n + beta) - digamma_d(beta);
+}
+
+__device__ __forceinline__ void nb_gamma_terms(int n, double beta, double& lg, double& dg) {
+  if (n <= 64) {
+    double s = 0.0, d = 0.0;
+    for (int m = 0; m < n; ++m) {
+      const double bm = beta + (double)m;
+      s += log(bm);
+      d += 1.0 / bm;
+    }
+    lg = s;
+    dg = d;
+  } else {
+    nb_gamma_big(n, beta, lg, dg);
+  }
+}
+
+// ---------------------------------------------------------- per-voxel fused
+template <int W>
+struct VoxelCore {
+  static constexpr int R = W == 1 ? 4 : 16;
+  float lam[W][3], pw[W], wgt[W][3], pm[W][4], preg[R];
+  float theta[4];
+  float x, lnx, ellr, u, logf;
+  float t6[W][6];
+
+  __device__ __forceinline__ void run(const VoxelArgs& a, const float* tab, long long i, float rho) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) t6[w][c] = a.tens[w * 6 + c][i];
+      float q;
+      eig3_values(t6[w], lam[w], q, pw[w]);
+      web_memberships(lam[w], a.steep, a.lam_th, wgt[w], pm[w]);
+    }
+    if (W == 1) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) preg[r] = pm[0][r];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) preg[4 * j + k] = pm[0][j] * pm[W - 1][k];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      float s = 0.f;
+#pragma unroll
+      for (int r = 0; r < R; ++r) s += preg[r] * tab[r * 4 + c];
+      theta[c] = s;
+    }
+    x = fmaxf(rho, a.x_floor);
+    lnx = ::logf(x);
+    ellr = lnx - ::logf(theta[2]);
+    u = expf(theta[1] * ellr);
+    logf = theta[0] * lnx - u;
+  }
+};
+
+template <int W>
+__global__ __launch_bounds__(256) void voxel_fwd_kernel(VoxelArgs a) {
+  __shared__ double red[4];
+  const long long c = blockIdx.y;
+  const long long nv = a.nv;
+  const float* tab = a.table + c * (W == 1 ? 16 : 64);
+  VoxelArgs b = a;
+  for (int k = 0; k < 6 * W; ++k) b.tens[k] = a.tens[k] + c * nv;
+  double sf = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x) {
+    VoxelCore<W> v;
+    v.run(b, tab, i, a.rho[c * nv + i]);
+    a.logf[c * nv + i] = v.logf;
+    a.beta[c * nv + i] = v.theta[3];
+    sf += (double)expf(v.logf);
+  }
+  const double s = block_sum(sf, red);
+  if (threadIdx.x == 0) a.partial[c * gridDim.x + blockIdx.x] = s;
+}
+
+// Likelihood pass: needs ln C = ln N_tr - ln sum f from the reduced partials.
+// The per-voxel negative-binomial terms are evaluated in float64 (a few
+// operations per voxel): their sum is what drives the Metropolis decision.
+__global__ __launch_bounds__(256) void likelihood_kernel(LikeArgs a) {
+  __shared__ double red[4];
+  const long long c = blockIdx.y;
+  const long long nv = a.nv;
+  const double lnc = a.scal[c * kScalStride + kScalLnC];
+  double sl = 0.0, sg = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x) {
+    const double lf = a.logf[c * nv + i];
+    const double beta = a.beta[c * nv + i];
+    const int n = a.counts[c * nv + i];
+    const double lnb = lnc + lf;
+    const double nb = exp(lnb);
+    const double l1p = log1p(nb / beta);
+    double lg, dg;
+    nb_gamma_terms(n, beta, lg, dg);
+    const double fn = (double)n;
+    sl += lg - (beta + fn) * l1p + fn * (lnb - log(beta));
+    sg += beta * (fn - nb) / (beta + nb);
+    if (a.nbar) a.nbar[c * nv + i] = (float)nb;
+  }
+  const double s1 = block_sum(sl, red);
+  const double s2 = block_sum(sg, red);
+  if (threadIdx.x == 0) {
+    a.partial[(c * gridDim.x + blockIdx.x) * 2 + 0] = s1;
+    a.partial[(c * gridDim.x + blockIdx.x) * 2 + 1] = s2;
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void voxel_bwd_kernel(VoxelArgs a) {
+  constexpr int R = W == 1 ? 4 : 16;
+  constexpr int NE = R * 4;
+  __shared__ double wpart[4][NE];
+  const long long c = blockIdx.y;
+  const long long nv = a.nv;
+  const float* tab = a.table + c * NE;
+  VoxelArgs b = a;
+  for (int k = 0; k < 6 * W; ++k) b.tens[k] = a.tens[k] + c * nv;
+  const double* sc = a.scal + c * kScalStride;
+  const double lnc = sc[kScalLnC];
+  const double gcoef = sc[kScalG] / sc[kScalNtr];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double acc = 0.0;   // lane e accumulates table-gradient entry e of its wave
+  for (long long i0 = blockIdx.x * (long long)blockDim.x; i0 < nv; i0 += (long long)gridDim.x * blockDim.x) {
+    const long long i = i0 + threadIdx.x;
+    double dth[4] = {0.0, 0.0, 0.0, 0.0};
+    float preg[R];
+    if (i < nv) {
+      VoxelCore<W> v;
+      const float rho = a.rho[c * nv + i];
+      v.run(b, tab, i, rho);
+#pragma unroll
+      for (int r = 0; r < R; ++r) preg[r] = v.preg[r];
+      // scalar bias / likelihood chain in float64 (its table sums cancel to
+      // ~1% at the data's own parameters, and the beta derivative cancels per
+      // voxel)
+      const int n = a.counts[c * nv + i];
+      const double fn = (double)n;
+      const double al = v.theta[0], ep = v.theta[1], rt = v.theta[2], beta = v.theta[3];
+      const double xd = (double)v.x;
+      const double lnx = log(xd);
+      const double ellr = lnx - log(rt);
+      const double u = exp(ep * ellr);
+      const double nb = exp(lnc + al * lnx - u);
+      const double l1p = log1p(nb / beta);
+      double lg, dg;
+      nb_gamma_terms(n, beta, lg, dg);
+      const double ghat = beta * (fn - nb) / (beta + nb);
+      const double af = ghat - gcoef * nb;                      // f dlogL/df
+      dth[0] = af * lnx;
+      dth[1] = -af * u * ellr;
+      dth[2] = af * u * ep / rt;
+      dth[3] = dg - l1p + (nb - fn) / (beta + nb);
+      const double dxv = af * (al - ep * u) / xd;
+      a.drho[c * nv + i] = rho > a.x_floor ? (float)dxv : 0.f;
+      float dp[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        dp[r] = (float)(tab[r * 4 + 0] * dth[0] + tab[r * 4 + 1] * dth[1] + tab[r * 4 + 2] * dth[2] +
+                        tab[r * 4 + 3] * dth[3]);
+      float dpw[W][4];
+      if (W == 1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dpw[0][r] = dp[r];
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            s0 += dp[4 * j + k] * v.pm[W - 1][k];
+            s1 += dp[4 * k + j] * v.pm[0][k];
+          }
+          dpw[0][j] = s0;
+          dpw[W - 1][j] = s1;
+        }
+      }
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        float gl[3];
+        const float dw[3] = {dpw[w][1] - dpw[w][0], dpw[w][2] - dpw[w][1], dpw[w][3] - dpw[w][2]};
+#pragma unroll
+        for (int m = 0; m < 3; ++m) gl[m] = dw[m] * a.steep * v.wgt[w][m] * (1.f - v.wgt[w][m]);
+        float gt[6];
+        eig3_grad(v.t6[w], v.lam[w], v.pw[w], gl, gt);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) a.dtens[w * 6 + k][c * nv + i] = gt[k];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) preg[r] = 0.f;
+    }
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const double s = wave_sum((double)preg[e / 4] * dth[e % 4]);
+      if (lane == e) acc += s;
+    }
+  }
+  if (lane < NE) wpart[wid][lane] = acc;
+  __syncthreads();
+  if (threadIdx.x < NE) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += wpart[w][threadIdx.x];
+    a.partial[(c * gridDim.x + blockIdx.x) * NE + threadIdx.x] = s;
+  }
+}
+
+// Sum of per-block partials in a fixed order (one workgroup per chain).
+// mode 0: sum f -> ln C; mode 1: (logL, G); mode 2: bias-table gradient.
+__global__ void finalize_kernel(FinalArgs a) {
+  __shared__ double red[4];
+  const long long c = blockIdx.x;
+  double* sc = a.scal + c * kScalStride;
+  if (a.mode == 0) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < a.nblk; i += blockDim.x) s += a.partial[c * a.nblk + i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+      sc[kScalSumF] = s;
+      sc[kScalLnC] = log(sc[kScalNtr]) - log(s);
+    }
+  } else if (a.mode == 1) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = threadIdx.x; i < a.nblk; i += blockDim.x) {
+      s1 += a.partial[(c * a.nblk + i) * 2];
+      s2 += a.partial[(c * a.nblk + i) * 2 + 1];
+    }
+    s1 = block_sum(s1, red);
+    s2 = block_sum(s2, red);
+    if (threadIdx.x == 0) {
+      const double logl = s1 - sc[kScalLgConst];
+      sc[kScalLogL] = logl;
+      sc[kScalG] = s2;
+      if (a.logl) a.logl[c] = logl;
+    }
+  } else {
+    const int ne = a.ne;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+      double s = 0.0;
+      for (int i = 0; i < a.nblk; ++i) s += a.partial[(c * a.nblk + i) * ne + e];
+      a.dtable[c * ne + e] = (float)s;
+    }
+  }
+}
+
+void launch_voxel_fwd(int w, const VoxelArgs& a, int chains, int nblk, hipStream_t s) {
+  dim3 g(nblk, chains);
+  if (w == 1) hipLaunchKernelGGL(voxel_fwd_kernel<1>, g, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(voxel_fwd_kernel<2>, g, dim3(256), 0, s, a);
+}
+void launch_voxel_bwd(int w, const VoxelArgs& a, int chains, int nblk, hipStream_t s) {
+  dim3 g(nblk, chains);
+  if (w == 1) hipLaunchKernelGGL(voxel_bwd_kernel<1>, g, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(voxel_bwd_kernel<2>, g, dim3(256), 0, s, a);
+}
+void launch_likelihood(const LikeArgs& a, int chains, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(likelihood_kernel, dim3(nblk, chains), dim3(256), 0, s, a);
+}
+void launch_finalize(const FinalArgs& a, int chains, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(chains), dim3(256), 0, s, a);
+}
+
+// ------------------------------------------------------ data-only constants
+__global__ void count_consts_kernel(const uint16_t* __restrict__ cnt, long long nv, double* partial) {
+  __shared__ double red[4];
+  double s0 = 0.0, s1 = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x) {
+    const double n = cnt[i];
+    s0 += n;
+    s1 += lgamma(n + 1.0);
+  }
+  const double a = block_sum(s0, red);
+  const double b = block_sum(s1, red);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x * 2] = a;
+    partial[blockIdx.x * 2 + 1] = b;
+  }
+}
+__global__ void count_consts_final(const double* partial, int nblk, double* sc) {
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < nblk; ++i) {
+      a += partial[2 * i];
+      b += partial[2 * i + 1];
+    }
+    sc[kScalNtr] = a;
+    sc[kScalLgConst] = b;
+  }
+}
+void launch_count_consts(const uint16_t* cnt, long long nv, double* partial, int nblk, double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(count_consts_kernel, dim3(nblk), dim3(256), 0, s, cnt, nv, partial);
+  hipLaunchKernelGGL(count_consts_final, dim3(1), dim3(64), 0, s, partial, nblk, scal);
+}
+
+// ------------------------------------------------------------------ leapfrog
+// p -= c (nu - dlogL/dnu)   (gradient of U = -logL + |nu|^2/2)
+__global__ void kick_kernel(LeapArgs a, float frac) {
+  const long long c = blockIdx.y;
+  const float e = a.step[a.chain0 + c] * frac;
+  const long long o = c * a.nv;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.nv; i += (long long)gridDim.x * blockDim.x)
+    a.p[o + i] -= e * (a.q[o + i] - a.g[o + i]);
+}
+__global__ void drift_kernel(LeapArgs a) {
+  const long long c = blockIdx.y;
+  const float e = a.step[a.chain0 + c];
+  const long long o = c * a.nv;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.nv; i += (long long)gridDim.x * blockDim.x)
+    a.q[o + i] += e * a.minv[o + i] * a.p[o + i];
+}
+// sum nu^2 / 2 + sum minv p^2 / 2 per block
+__global__ void energy_kernel(LeapArgs a) {
+  __shared__ double red[4];
+  const long long c = blockIdx.y;
+  const long long o = c * a.nv;
+  double s = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.nv; i += (long long)gridDim.x * blockDim.x) {
+    const double q = a.q[o + i], p = a.p[o + i];
+    s += 0.5 * q * q + 0.5 * (double)a.minv[o + i] * p * p;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) a.partial[c * gridDim.x + blockIdx.x] = s;
+}
+void launch_kick(const LeapArgs& a, int chains, float frac, hipStream_t s) {
+  hipLaunchKernelGGL(kick_kernel, dim3(grid_for(a.nv, 256, 4096), chains), dim3(256), 0, s, a, frac);
+}
+void launch_drift(const LeapArgs& a, int chains, hipStream_t s) {
+  hipLaunchKernelGGL(drift_kernel, dim3(grid_for(a.nv, 256, 4096), chains), dim3(256), 0, s, a);
+}
+void launch_energy(const LeapArgs& a, int chains, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(energy_kernel, dim3(nblk, chains), dim3(256), 0, s, a);
+}
+
+// Free bias parameters: one workgroup per chain.
+//   mode 0: table = base with tied entries exp(u)
+//   mode 1: half kick of p_u with frac * step
+//   mode 2: drift of u
+//   mode 3: Hamiltonian: H = -logL + field energy partials + prior + kinetic(u)
+__global__ void params_kernel(ParamArgs a, int mode, float frac, int nblk_energy, double* hout) {
+  const int c = blockIdx.x;
+  const int ne = a.ne, nf = a.nfree;
+  float* u = a.u + c * nf;
+  float* pu = a.pu + c * nf;
+  const float* mi = a.minv_u + c * nf;
+  if (mode == 0) {
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+      const int f = a.tie[e];
+      a.table[c * ne + e] = f >= 0 ? expf(u[f]) : a.base[c * ne + e];
+    }
+  } else if (mode == 1) {
+    const float e = a.step[c] * frac;
+    for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+      double g = 0.0;
+      for (int k = 0; k < ne; ++k)
+        if (a.tie[k] == f) g += (double)a.dtable[c * ne + k] * (double)a.table[c * ne + k];
+      const double du = -g + ((double)u[f] - a.mu[f]) / (a.sigma[f] * a.sigma[f]);
+      pu[f] -= e * (float)du;
+    }
+  } else if (mode == 2) {
+    const float e = a.step[c];
+    for (int f = threadIdx.x; f < nf; f += blockDim.x) u[f] += e * mi[f] * pu[f];
+  } else {
+    if (threadIdx.x == 0) {
+      double h = -a.scal[c * kScalStride + kScalLogL];
+      for (int i = 0; i < nblk_energy; ++i) h += a.epartial[c * nblk_energy + i];
+      for (int f = 0; f < nf; ++f) {
+        const double d = (double)u[f] - a.mu[f];
+        h += d * d / (2.0 * a.sigma[f] * a.sigma[f]);
+        h += 0.5 * (double)mi[f] * (double)pu[f] * (double)pu[f];
+      }
+      hout[c] = h;
+    }
+  }
+}
+void launch_params(const ParamArgs& a, int chains, int mode, float frac, int nblk_energy, double* hout,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(params_kernel, dim3(chains), dim3(64), 0, s, a, mode, frac, nblk_energy, hout);
+}
+
+__global__ void trace3_kernel(const float* a, const float* b, const float* c, float* out, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = a[i] + b[i] + c[i];
+}
+void launch_trace3(const float* a, const float* b, const float* c, float* out, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(trace3_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, a, b, c, out, n);
+}
+
+// Copy of a padded half spectrum into the dense [n][n][n/2+1] layout and back.
+__global__ void spec_repack_kernel(const float2* __restrict__ src, float2* __restrict__ dst, int n, int sp, int dp,
+                                   long long rows) {
+  const int m1 = n / 2 + 1;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < rows * m1; i += (long long)gridDim.x * blockDim.x) {
+    const long long r = i / m1;
+    const int k = (int)(i - r * m1);
+    dst[r * dp + k] = src[r * sp + k];
+  }
+}
+void launch_spec_repack(const float2* src, float2* dst, int n, int sp, int dp, long long rows, hipStream_t s) {
+  hipLaunchKernelGGL(spec_repack_kernel, dim3(grid_for(rows * (n / 2 + 1), 256, 16384)), dim3(256), 0, s, src, dst, n,
+                     sp, dp, rows);
+}
+
+}  // namespace fzw

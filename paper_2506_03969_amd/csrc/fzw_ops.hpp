@@ -1,0 +1,115 @@
+// Argument blocks and launchers of the non-FFT kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fzw {
+
+// per-chain float64 scalars kept on the device
+enum { kScalNtr = 0, kScalLgConst = 1, kScalSumF = 2, kScalLnC = 3, kScalLogL = 4, kScalG = 5, kScalStride = 8 };
+
+struct LptArgs {
+  const float* phi[6];
+  float* s2;     // forward: output S2; backward: input cotangent of S2
+  float* dsc;    // forward: output d_SC; backward: input cotangent of d_SC
+  float* dphi[6];
+  float d1, tau;
+  long long n;
+};
+
+struct CicArgs {
+  const float* psi[3];
+  float scale[3];        // displacement -> cell units per axis (RSD factor included)
+  int n;
+  long long nv;
+  int* count;            // [chains][nv]
+  int* offset;           // [chains][nv+1]
+  int* bsum;             // [chains][nv/4096 rounded up]
+  int2* keyslot;         // [chains][nv]
+  float4* sorted;        // [chains][nv]
+  float* rho;            // [chains][nv]
+  const float* drho;     // adjoint input
+  float* dpsi[3];        // adjoint output
+};
+
+struct VoxelArgs {
+  const float* tens[12];
+  float* dtens[12];
+  const float* rho;
+  const float* table;    // [chains][R*4]
+  const uint16_t* counts;
+  const double* scal;
+  float* logf;
+  float* beta;
+  float* drho;
+  double* partial;
+  float x_floor, steep, lam_th;
+  long long nv;
+};
+
+struct LikeArgs {
+  const float* logf;
+  const float* beta;
+  const uint16_t* counts;
+  const double* scal;
+  double* partial;
+  float* nbar;
+  long long nv;
+};
+
+struct FinalArgs {
+  int mode;
+  const double* partial;
+  int nblk;
+  double* scal;
+  double* logl;
+  float* dtable;
+  int ne;
+};
+
+struct LeapArgs {
+  float* q;
+  float* p;
+  const float* g;
+  const float* minv;
+  const float* step;
+  int chain0;
+  long long nv;
+  double* partial;
+};
+
+struct ParamArgs {
+  float* u;
+  float* pu;
+  const float* minv_u;
+  const double* mu;
+  const double* sigma;
+  const int* tie;
+  const float* base;
+  float* table;
+  const float* dtable;
+  const float* step;
+  const double* scal;
+  const double* epartial;
+  int ne, nfree;
+};
+
+void launch_fill_i32(int* p, long long n, int v, hipStream_t s);
+void launch_fill_f32(float* p, long long n, float v, hipStream_t s);
+void launch_lpt_fwd(const LptArgs& a, hipStream_t s);
+void launch_lpt_bwd(const LptArgs& a, hipStream_t s);
+void launch_cic_deposit(const CicArgs& a, int chains, hipStream_t s);
+void launch_cic_adjoint(const CicArgs& a, int chains, hipStream_t s);
+void launch_voxel_fwd(int w, const VoxelArgs& a, int chains, int nblk, hipStream_t s);
+void launch_voxel_bwd(int w, const VoxelArgs& a, int chains, int nblk, hipStream_t s);
+void launch_likelihood(const LikeArgs& a, int chains, int nblk, hipStream_t s);
+void launch_finalize(const FinalArgs& a, int chains, hipStream_t s);
+void launch_count_consts(const uint16_t* cnt, long long nv, double* partial, int nblk, double* scal, hipStream_t s);
+void launch_kick(const LeapArgs& a, int chains, float frac, hipStream_t s);
+void launch_drift(const LeapArgs& a, int chains, hipStream_t s);
+void launch_energy(const LeapArgs& a, int chains, int nblk, hipStream_t s);
+void launch_params(const ParamArgs& a, int chains, int mode, float frac, int nblk_energy, double* hout, hipStream_t s);
+void launch_trace3(const float* a, const float* b, const float* c, float* out, long long n, hipStream_t s);
+void launch_spec_repack(const float2* src, float2* dst, int n, int sp, int dp, long long rows, hipStream_t s);
+
+}  // namespace fzw

@@ -1,0 +1,1080 @@
+// Host runtime of the fuzzy-web likelihood library: plans, workspace, spectral
+// tables, the stage schedule of the forward model and of its adjoint, the
+// leapfrog trajectory (captured as a HIP graph) and the C ABI of fzw.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/fzw.h"
+#include "fzw_internal.hpp"
+#include "fzw_ops.hpp"
+
+namespace fzw {
+
+static thread_local std::string g_last_error;
+
+struct Error : std::runtime_error {
+  fzw_status code;
+  Error(fzw_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(expr)                                                                             \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) {                                                                      \
+      (void)hipGetLastError();                                                                   \
+      throw Error(e_ == hipErrorOutOfMemory ? FZW_E_OOM : FZW_E_HIP,                            \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                           \
+    }                                                                                            \
+  } while (0)
+
+// radial tables
+enum { TAB_H = 0, TAB_INVK2 = 1, TAB_K = 2, TAB_1MK = 3, TAB_WEB0 = 4, TAB_WEB1 = 5, NTAB = 6 };
+// stage scratch spectra
+constexpr int kNSpec = 13;
+
+// ------------------------------------------------------------ power spectrum
+// Linear matter power spectrum with the BBKS transfer function (Bardeen, Bond,
+// Kaiser & Szalay 1986), shape Gamma = Omega_m h, tilt n_s, normalised to
+// sigma8 with a top-hat of 8 Mpc/h (composite Simpson in ln k, 1e-5..1e2 h/Mpc).
+static double bbks(double k, double om, double h) {
+  if (k <= 0) return 1.0;
+  const double q = k / (om * h);
+  const double a = std::log1p(2.34 * q) / (2.34 * q);
+  const double b = 1.0 + 3.89 * q + std::pow(16.1 * q, 2) + std::pow(5.46 * q, 3) + std::pow(6.71 * q, 4);
+  return a * std::pow(b, -0.25);
+}
+static double tophat(double x) {
+  if (std::fabs(x) < 1e-4) return 1.0 - x * x / 10.0;
+  return 3.0 * (std::sin(x) - x * std::cos(x)) / (x * x * x);
+}
+static double power_amplitude(const fzw_cosmo& c) {
+  const int n = 400000;  // even number of intervals
+  const double a = std::log(1e-5), b = std::log(1e2), dh = (b - a) / n;
+  double s = 0.0;
+  for (int i = 0; i <= n; ++i) {
+    const double lk = a + i * dh, k = std::exp(lk);
+    const double t = bbks(k, c.omega_m, c.h);
+    const double f = k * k * k * std::pow(k, c.n_s) * t * t * std::pow(tophat(8.0 * k), 2);
+    const double w = (i == 0 || i == n) ? 1.0 : (i % 2 ? 4.0 : 2.0);
+    s += w * f;
+  }
+  s *= dh / 3.0 / (2.0 * M_PI * M_PI);
+  return c.sigma8 * c.sigma8 / s;
+}
+
+struct Group {
+  int n = 0;
+  double box = 0;
+  int c0 = 0, nc = 0;
+  long long nv = 0;          // n^3
+  int P = 0;                 // spectrum row pitch
+  long long ns = 0;          // spectrum elements per chain
+  int nblk = 0;              // blocks of the per-voxel kernels
+  float* tabs = nullptr;
+  int tab_stride = 0;
+  float2* tw_full = nullptr;
+  float2* tw_half = nullptr;
+  // real fields [nc][nv]
+  float* phi[6] = {};
+  float* s2 = nullptr;
+  float* dsc = nullptr;
+  float* psi[3] = {};
+  float* rho = nullptr;
+  float* tens[12] = {};
+  float* logf = nullptr;
+  float* beta = nullptr;
+  float* drho_dir = nullptr;
+  float* drho = nullptr;
+  float2* spec[kNSpec] = {};
+  int* count = nullptr;
+  int* offset = nullptr;
+  int* bsum = nullptr;
+  int2* keyslot = nullptr;
+  float4* sorted = nullptr;
+};
+
+}  // namespace fzw
+
+using namespace fzw;
+
+struct fzw_plan {
+  int n_chains = 0;
+  int W = 1, R = 4;
+  fzw_cosmo cosmo{};
+  fzw_web web{};
+  hipStream_t stream = nullptr;       // work is enqueued here
+  hipStream_t user_stream = nullptr;  // the caller's stream
+  hipStream_t cap_stream = nullptr;   // private stream for graph capture and replay
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  double amp = 0;
+  std::vector<Group> groups;
+  std::vector<long long> chain_off;   // voxel offset per chain
+  std::vector<int> chain_group;
+  std::vector<bool> counts_set;
+  long long total_vox = 0;
+  uint16_t* counts = nullptr;
+  double* scal = nullptr;             // [n_chains][kScalStride]
+  double* partial = nullptr;
+  size_t partial_elems = 0;
+  float* dnu_tmp = nullptr;           // leapfrog gradient
+  float* table_tmp = nullptr;         // leapfrog bias tables
+  float* dtable_tmp = nullptr;
+  double* epartial = nullptr;         // leapfrog energy partials [n_chains][kEBlk]
+  int* tie = nullptr;
+  double* mu = nullptr;
+  double* sigma = nullptr;
+  int nfree = -1;
+  std::vector<void*> allocs;
+  size_t ws_bytes = 0;
+  struct GraphEntry {
+    hipGraph_t g;
+    hipGraphExec_t e;
+  };
+  std::map<std::vector<uintptr_t>, GraphEntry> graphs;
+  // per-kernel-class timing with HIP events (off unless enabled)
+  bool timing = false;
+  std::vector<hipEvent_t> evpool;
+  size_t evused = 0;
+  struct TimingRec {
+    int klass;
+    double bytes;
+    hipEvent_t a, b;
+  };
+  std::vector<TimingRec> recs;
+};
+
+namespace {
+
+constexpr int kEBlk = 256;
+
+template <class T>
+T* dalloc(fzw_plan* p, size_t count) {
+  void* ptr = nullptr;
+  const size_t bytes = count * sizeof(T);
+  hipError_t e = hipMalloc(&ptr, bytes > 0 ? bytes : 16);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(FZW_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  p->allocs.push_back(ptr);
+  p->ws_bytes += bytes;
+  return static_cast<T*>(ptr);
+}
+
+// Records HIP events around a launch of kernel class `klass` on the plan's
+// stream when timing is enabled; `bytes` is the launch's algorithmic traffic.
+struct Timed {
+  fzw_plan* p;
+  int idx = -1;
+  Timed(fzw_plan* pl, int klass, double bytes) : p(pl) {
+    if (!p || !p->timing) return;
+    while (p->evpool.size() < p->evused + 2) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      p->evpool.push_back(e);
+    }
+    fzw_plan::TimingRec r{klass, bytes, p->evpool[p->evused], p->evpool[p->evused + 1]};
+    p->evused += 2;
+    HIPCHK(hipEventRecord(r.a, p->stream));
+    p->recs.push_back(r);
+    idx = (int)p->recs.size() - 1;
+  }
+  ~Timed() {
+    if (idx >= 0) (void)hipEventRecord(p->recs[idx].b, p->stream);
+  }
+};
+
+double spec_bytes(const Group& g) { return (double)g.nc * g.n * g.n * (g.n / 2 + 1) * 8.0; }
+double field_bytes(const Group& g) { return (double)g.nc * g.nv * 4.0; }
+
+bool supported_n(int n) {
+  return n == 16 || n == 32 || n == 64 || n == 96 || n == 128 || n == 256 || n == 512;
+}
+
+void build_tables(fzw_plan* p, Group& g) {
+  const int n = g.n;
+  const int half = n / 2;
+  const int n2max = 3 * half * half;
+  g.tab_stride = n2max + 1;
+  std::vector<float> tab((size_t)NTAB * g.tab_stride, 0.f);
+  const double kf = 2.0 * M_PI / g.box;
+  const double dx = g.box / n;
+  for (int q = 0; q <= n2max; ++q) {
+    const double k2 = kf * kf * q;
+    const double k = std::sqrt(k2);
+    double h = 0, ik2 = 0;
+    if (q > 0) {
+      const double t = bbks(k, p->cosmo.omega_m, p->cosmo.h);
+      const double pk = p->amp * std::pow(k, p->cosmo.n_s) * t * t;
+      h = std::sqrt(pk / (dx * dx * dx));
+      ik2 = 1.0 / k2;
+    }
+    const double kern = std::exp(-0.5 * k2 * p->cosmo.r_s * p->cosmo.r_s);
+    tab[(size_t)TAB_H * g.tab_stride + q] = (float)h;
+    tab[(size_t)TAB_INVK2 * g.tab_stride + q] = (float)ik2;
+    tab[(size_t)TAB_K * g.tab_stride + q] = (float)kern;
+    tab[(size_t)TAB_1MK * g.tab_stride + q] = (float)(1.0 - kern);
+    for (int w = 0; w < p->W; ++w) {
+      const double r = p->web.smooth_r[w];
+      const double wg = std::exp(-0.5 * k2 * r * r);
+      double m;
+      if (p->web.kind[w] == FZW_WEB_PHI) m = wg * ik2;
+      else m = p->web.ell[w] * p->web.ell[w] * wg;
+      tab[(size_t)(TAB_WEB0 + w) * g.tab_stride + q] = (float)m;
+    }
+  }
+  g.tabs = dalloc<float>(p, tab.size());
+  HIPCHK(hipMemcpy(g.tabs, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice));
+  std::vector<float2> tf(n), th(half);
+  for (int k = 0; k < n; ++k) {
+    const double a = -2.0 * M_PI * k / n;
+    tf[k] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  for (int k = 0; k < half; ++k) {
+    const double a = -2.0 * M_PI * k / half;
+    th[k] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  g.tw_full = dalloc<float2>(p, n);
+  g.tw_half = dalloc<float2>(p, half);
+  HIPCHK(hipMemcpy(g.tw_full, tf.data(), n * sizeof(float2), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(g.tw_half, th.data(), half * sizeof(float2), hipMemcpyHostToDevice));
+}
+
+void alloc_group(fzw_plan* p, Group& g) {
+  const size_t nf = (size_t)g.nc * g.nv;
+  const size_t nsp = (size_t)g.nc * g.ns;
+  for (auto& f : g.phi) f = dalloc<float>(p, nf);
+  g.s2 = dalloc<float>(p, nf);
+  g.dsc = dalloc<float>(p, nf);
+  for (auto& f : g.psi) f = dalloc<float>(p, nf);
+  g.rho = dalloc<float>(p, nf);
+  for (int k = 0; k < 6 * p->W; ++k) g.tens[k] = dalloc<float>(p, nf);
+  g.logf = dalloc<float>(p, nf);
+  g.beta = dalloc<float>(p, nf);
+  g.drho_dir = dalloc<float>(p, nf);
+  g.drho = dalloc<float>(p, nf);
+  for (auto& s : g.spec) s = dalloc<float2>(p, nsp);
+  g.count = dalloc<int>(p, nf);
+  g.offset = dalloc<int>(p, (size_t)g.nc * (g.nv + 1));
+  g.bsum = dalloc<int>(p, (size_t)g.nc * ((g.nv + 4095) / 4096));
+  g.keyslot = dalloc<int2>(p, nf);
+  g.sorted = dalloc<float4>(p, nf);
+}
+
+// ------------------------------------------------------------- pass helpers
+struct Pass {
+  PassArgs a{};
+  Pass() {
+    for (auto& r : a.A)
+      for (auto& o : r) o = spec_zero();
+    for (auto& r : a.B)
+      for (auto& o : r) o = spec_zero();
+  }
+  Pass& in(const float2* p, bool fft) {
+    a.in_fft |= fft ? (1u << a.nin) : 0u;
+    a.in[a.nin++] = p;
+    return *this;
+  }
+  Pass& out(float2* p, bool fft) {
+    a.out_fft |= fft ? (1u << a.nout) : 0u;
+    a.out[a.nout++] = p;
+    return *this;
+  }
+};
+
+thread_local fzw_plan* t_plan = nullptr;   // plan whose stages are being enqueued
+
+void run_pass(const Group& g, int axis, Pass& ps, int nmid, hipStream_t s) {
+  Timed tm(t_plan, FZW_K_XYPASS, (ps.a.nin + ps.a.nout) * spec_bytes(g));
+  ps.a.nmid = nmid;
+  ps.a.chain_stride = g.ns;
+  ps.a.tabs = g.tabs;
+  ps.a.tab_stride = g.tab_stride;
+  ps.a.kf = (float)(2.0 * M_PI / g.box);
+  launch_xy_pass(g.n, axis, ps.a, g.nc, g.tw_full, s);
+}
+
+// pure forward or inverse transform of k arrays along an axis, in place
+void pure_pass(const Group& g, int axis, bool inverse, float2* const* arr, int k, hipStream_t s) {
+  int done = 0;
+  while (done < k) {
+    const int m = std::min(kMaxMid, k - done);
+    Pass ps;
+    for (int i = 0; i < m; ++i) ps.in(arr[done + i], !inverse);
+    for (int i = 0; i < m; ++i) ps.out(arr[done + i], inverse);
+    for (int i = 0; i < m; ++i) {
+      ps.a.A[i][i] = spec_const(1.f);
+      ps.a.B[i][i] = spec_const(1.f);
+    }
+    run_pass(g, axis, ps, m, s);
+    done += m;
+  }
+}
+
+void zf(const Group& g, float* const* in, float2* const* out, int k, hipStream_t s) {
+  Timed tm(t_plan, FZW_K_ZPASS, k * (field_bytes(g) + spec_bytes(g)));
+  launch_zpass_r2c(g.n, (const float* const*)in, out, k, g.nc, g.nv, g.ns, g.tw_half, g.tw_full, s);
+}
+void zi(const Group& g, float2* const* in, float* const* out, int k, hipStream_t s) {
+  Timed tm(t_plan, FZW_K_ZPASS, k * (field_bytes(g) + spec_bytes(g)));
+  launch_zpass_c2r(g.n, (const float2* const*)in, out, k, g.nc, g.ns, g.nv, g.tw_half, g.tw_full, s);
+}
+
+// axis ids for SpecOp
+constexpr int X = 0, Y = 1, Z = 2, NONE = -1;
+
+// ------------------------------------------------------------- forward model
+void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, float* nbar, double* logl) {
+  hipStream_t s = p->stream;
+  const float invn3 = (float)(1.0 / ((double)g.nv));
+  const float d1 = (float)p->cosmo.d1;
+  float2** sp = g.spec;
+  // Appendix A: delta_L spectrum = h(k) rfftn(nu)
+  {
+    float* src[1] = {const_cast<float*>(nu)};
+    zf(g, src, &sp[0], 1, s);
+    pure_pass(g, Y, false, &sp[0], 1, s);
+    Pass ps;
+    ps.in(sp[0], true).out(sp[1], false);
+    ps.a.A[0][0] = spec(1.f, 0.f, NONE, NONE, TAB_H, NONE);
+    ps.a.B[0][0] = spec_const(1.f);
+    run_pass(g, X, ps, 1, s);
+  }
+  // Section 2.3: Hessian of the first-order potential, phi_ij = k_i k_j / k^2 delta_L
+  {
+    Pass ps;
+    ps.in(sp[1], false).out(sp[2], true).out(sp[3], true).out(sp[4], true);
+    ps.a.A[0][0] = spec_const(1.f);
+    ps.a.B[0][0] = spec(invn3, 0.f, X, X, TAB_INVK2, NONE);
+    ps.a.B[1][0] = spec(invn3, 0.f, X, NONE, TAB_INVK2, NONE);
+    ps.a.B[2][0] = spec(invn3, 0.f, NONE, NONE, TAB_INVK2, NONE);
+    run_pass(g, X, ps, 1, s);
+    Pass py;
+    py.in(sp[2], false).in(sp[3], false).in(sp[4], false);
+    for (int i = 0; i < 3; ++i) py.a.A[i][i] = spec_const(1.f);
+    // outputs in the order xx, yy, zz, xy, xz, yz
+    for (int o = 0; o < 6; ++o) py.out(sp[5 + o], true);
+    py.a.B[0][0] = spec_const(1.f);                      // xx
+    py.a.B[1][2] = spec(1.f, 0.f, Y, Y, NONE, NONE);     // yy
+    py.a.B[2][2] = spec(1.f, 0.f, Z, Z, NONE, NONE);     // zz
+    py.a.B[3][1] = spec(1.f, 0.f, Y, NONE, NONE, NONE);  // xy
+    py.a.B[4][1] = spec(1.f, 0.f, Z, NONE, NONE, NONE);  // xz
+    py.a.B[5][2] = spec(1.f, 0.f, Y, Z, NONE, NONE);     // yz
+    run_pass(g, Y, py, 3, s);
+    zi(g, &sp[5], g.phi, 6, s);
+  }
+  // 2LPT source and spherical-collapse divergence
+  {
+    LptArgs la{};
+    for (int c = 0; c < 6; ++c) la.phi[c] = g.phi[c];
+    la.s2 = g.s2;
+    la.dsc = g.dsc;
+    la.d1 = d1;
+    la.tau = (float)p->cosmo.tau_sc;
+    la.n = (long long)g.nc * g.nv;
+    Timed tm(p, FZW_K_LPT, 8 * field_bytes(g));
+    launch_lpt_fwd(la, s);
+  }
+  // ALPT blend -> Psi (Section 2.3)
+  {
+    float* src[2] = {g.s2, g.dsc};
+    zf(g, src, &sp[2], 2, s);
+    pure_pass(g, Y, false, &sp[2], 2, s);
+    Pass ps;
+    ps.in(sp[2], true).in(sp[3], true).in(sp[1], false);
+    ps.a.A[0][0] = spec((float)(3.0 / 7.0) * d1 * d1 * invn3, 0.f, NONE, NONE, TAB_K, TAB_INVK2);
+    ps.a.A[0][1] = spec(-invn3, 0.f, NONE, NONE, TAB_1MK, TAB_INVK2);
+    ps.a.A[0][2] = spec(d1 * invn3, 0.f, NONE, NONE, TAB_K, TAB_INVK2);
+    ps.out(sp[4], true).out(sp[5], true);
+    ps.a.B[0][0] = spec(0.f, 1.f, X, NONE, NONE, NONE);  // i k_x
+    ps.a.B[1][0] = spec_const(1.f);
+    run_pass(g, X, ps, 1, s);
+    Pass py;
+    py.in(sp[4], false).in(sp[5], false);
+    py.a.A[0][0] = spec_const(1.f);
+    py.a.A[1][1] = spec_const(1.f);
+    py.out(sp[6], true).out(sp[7], true).out(sp[8], true);
+    py.a.B[0][0] = spec_const(1.f);
+    py.a.B[1][1] = spec(0.f, 1.f, Y, NONE, NONE, NONE);
+    py.a.B[2][1] = spec(0.f, 1.f, Z, NONE, NONE, NONE);
+    run_pass(g, Y, py, 2, s);
+    zi(g, &sp[6], g.psi, 3, s);
+  }
+  // CIC deposit (with plane-parallel RSD)
+  {
+    CicArgs ca{};
+    for (int d = 0; d < 3; ++d) {
+      ca.psi[d] = g.psi[d];
+      const double f = (p->cosmo.rsd_axis == d) ? (1.0 + p->cosmo.f_growth) : 1.0;
+      ca.scale[d] = (float)(f * g.n / g.box);
+    }
+    ca.n = g.n;
+    ca.nv = g.nv;
+    ca.count = g.count;
+    ca.offset = g.offset;
+    ca.bsum = g.bsum;
+    ca.keyslot = g.keyslot;
+    ca.sorted = g.sorted;
+    ca.rho = g.rho;
+    Timed tm(p, FZW_K_CIC, 4 * field_bytes(g));
+    launch_cic_deposit(ca, g.nc, s);
+  }
+  // Web tensors (Section 2.8): T^w_ij = k_i k_j m_w(k) rho_k
+  {
+    float* src[1] = {g.rho};
+    zf(g, src, &sp[0], 1, s);
+    pure_pass(g, Y, false, &sp[0], 1, s);
+    Pass ps;
+    ps.in(sp[0], true);
+    ps.a.A[0][0] = spec_const(1.f);
+    for (int w = 0; w < p->W; ++w) {
+      ps.out(sp[1 + 3 * w], true).out(sp[2 + 3 * w], true).out(sp[3 + 3 * w], true);
+      ps.a.B[3 * w + 0][0] = spec(invn3, 0.f, X, X, TAB_WEB0 + w, NONE);
+      ps.a.B[3 * w + 1][0] = spec(invn3, 0.f, X, NONE, TAB_WEB0 + w, NONE);
+      ps.a.B[3 * w + 2][0] = spec(invn3, 0.f, NONE, NONE, TAB_WEB0 + w, NONE);
+    }
+    run_pass(g, X, ps, 1, s);
+    for (int w = 0; w < p->W; ++w) {
+      Pass py;
+      py.in(sp[1 + 3 * w], false).in(sp[2 + 3 * w], false).in(sp[3 + 3 * w], false);
+      for (int i = 0; i < 3; ++i) py.a.A[i][i] = spec_const(1.f);
+      for (int o = 0; o < 6; ++o) py.out(sp[7 + o], true);
+      py.a.B[0][0] = spec_const(1.f);
+      py.a.B[1][2] = spec(1.f, 0.f, Y, Y, NONE, NONE);
+      py.a.B[2][2] = spec(1.f, 0.f, Z, Z, NONE, NONE);
+      py.a.B[3][1] = spec(1.f, 0.f, Y, NONE, NONE, NONE);
+      py.a.B[4][1] = spec(1.f, 0.f, Z, NONE, NONE, NONE);
+      py.a.B[5][2] = spec(1.f, 0.f, Y, Z, NONE, NONE);
+      run_pass(g, Y, py, 3, s);
+      zi(g, &sp[7], &g.tens[6 * w], 6, s);
+    }
+  }
+  // Fused per-voxel web / bias forward, then normalisation and likelihood
+  {
+    VoxelArgs va{};
+    for (int k = 0; k < 6 * p->W; ++k) va.tens[k] = g.tens[k];
+    va.rho = g.rho;
+    va.table = bias + (size_t)g.c0 * p->R * 4;
+    va.logf = g.logf;
+    va.beta = g.beta;
+    va.partial = p->partial;
+    va.x_floor = (float)p->cosmo.x_floor;
+    va.steep = (float)p->web.steepness;
+    va.lam_th = (float)p->web.lambda_th;
+    va.nv = g.nv;
+    {
+      Timed tm(p, FZW_K_VOXEL_FWD, (3 + 6 * p->W) * field_bytes(g));
+      launch_voxel_fwd(p->W, va, g.nc, g.nblk, s);
+    }
+    FinalArgs fa{};
+    fa.mode = 0;
+    fa.partial = p->partial;
+    fa.nblk = g.nblk;
+    fa.scal = p->scal + (size_t)g.c0 * kScalStride;
+    launch_finalize(fa, g.nc, s);
+    LikeArgs la{};
+    la.logf = g.logf;
+    la.beta = g.beta;
+    la.counts = p->counts + p->chain_off[g.c0];
+    la.scal = p->scal + (size_t)g.c0 * kScalStride;
+    la.partial = p->partial;
+    la.nbar = nbar ? nbar + p->chain_off[g.c0] : nullptr;
+    la.nv = g.nv;
+    {
+      Timed tm(p, FZW_K_LIKE, (2.5 + (nbar ? 1 : 0)) * field_bytes(g));
+      launch_likelihood(la, g.nc, g.nblk, s);
+    }
+    fa.mode = 1;
+    fa.logl = logl ? logl + g.c0 : nullptr;
+    launch_finalize(fa, g.nc, s);
+  }
+}
+
+// ------------------------------------------------------------------ adjoint
+void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* dbias) {
+  hipStream_t s = p->stream;
+  const float invn3 = (float)(1.0 / ((double)g.nv));
+  const float d1 = (float)p->cosmo.d1;
+  const int W = p->W;
+  float2** sp = g.spec;
+  // per-voxel backward: d rho (direct), d T (in place over T), table gradient
+  {
+    VoxelArgs va{};
+    for (int k = 0; k < 6 * W; ++k) {
+      va.tens[k] = g.tens[k];
+      va.dtens[k] = g.tens[k];
+    }
+    va.rho = g.rho;
+    va.table = bias + (size_t)g.c0 * p->R * 4;
+    va.counts = p->counts + p->chain_off[g.c0];
+    va.scal = p->scal + (size_t)g.c0 * kScalStride;
+    va.drho = g.drho_dir;
+    va.partial = p->partial;
+    va.x_floor = (float)p->cosmo.x_floor;
+    va.steep = (float)p->web.steepness;
+    va.lam_th = (float)p->web.lambda_th;
+    va.nv = g.nv;
+    {
+      Timed tm(p, FZW_K_VOXEL_BWD, (2.5 + 12 * W) * field_bytes(g));
+      launch_voxel_bwd(W, va, g.nc, g.nblk, s);
+    }
+    FinalArgs fa{};
+    fa.mode = 2;
+    fa.partial = p->partial;
+    fa.nblk = g.nblk;
+    fa.scal = p->scal + (size_t)g.c0 * kScalStride;
+    fa.dtable = dbias + (size_t)g.c0 * p->R * 4;
+    fa.ne = p->R * 4;
+    launch_finalize(fa, g.nc, s);
+  }
+  // web adjoint: d rho_k = sum_w m_w sum_ij k_i k_j rfft(dT_ij) + rfft(d rho_direct)
+  {
+    zf(g, g.tens, &sp[0], 6 * W, s);
+    float* dd[1] = {g.drho_dir};
+    zf(g, dd, &sp[12], 1, s);
+    for (int w = 0; w < W; ++w) {
+      Pass py;
+      for (int i = 0; i < 6; ++i) py.in(sp[6 * w + i], true);
+      py.a.A[0][0] = spec_const(1.f);                          // G2 = T_xx
+      py.a.A[1][3] = spec(1.f, 0.f, Y, NONE, NONE, NONE);      // G1 = k_y T_xy + k_z T_xz
+      py.a.A[1][4] = spec(1.f, 0.f, Z, NONE, NONE, NONE);
+      py.a.A[2][1] = spec(1.f, 0.f, Y, Y, NONE, NONE);         // G0 = k_y^2 T_yy + k_z^2 T_zz + k_y k_z T_yz
+      py.a.A[2][2] = spec(1.f, 0.f, Z, Z, NONE, NONE);
+      py.a.A[2][5] = spec(1.f, 0.f, Y, Z, NONE, NONE);
+      for (int o = 0; o < 3; ++o) {
+        py.out(sp[6 * w + o], false);
+        py.a.B[o][o] = spec_const(1.f);
+      }
+      run_pass(g, Y, py, 3, s);
+    }
+    pure_pass(g, Y, false, &sp[12], 1, s);
+    Pass ps;
+    for (int w = 0; w < W; ++w) {
+      ps.in(sp[6 * w + 0], true).in(sp[6 * w + 1], true).in(sp[6 * w + 2], true);
+      ps.a.A[0][3 * w + 0] = spec(invn3, 0.f, X, X, TAB_WEB0 + w, NONE);
+      ps.a.A[0][3 * w + 1] = spec(invn3, 0.f, X, NONE, TAB_WEB0 + w, NONE);
+      ps.a.A[0][3 * w + 2] = spec(invn3, 0.f, NONE, NONE, TAB_WEB0 + w, NONE);
+    }
+    ps.in(sp[12], true);
+    ps.a.A[0][3 * W] = spec_const(invn3);
+    ps.out(sp[0], true);
+    ps.a.B[0][0] = spec_const(1.f);
+    run_pass(g, X, ps, 1, s);
+    pure_pass(g, Y, true, &sp[0], 1, s);
+    zi(g, &sp[0], &g.drho, 1, s);
+  }
+  // CIC adjoint -> d Psi (in place over Psi)
+  {
+    CicArgs ca{};
+    for (int d = 0; d < 3; ++d) {
+      ca.psi[d] = g.psi[d];
+      ca.dpsi[d] = g.psi[d];
+      const double f = (p->cosmo.rsd_axis == d) ? (1.0 + p->cosmo.f_growth) : 1.0;
+      ca.scale[d] = (float)(f * g.n / g.box);
+    }
+    ca.n = g.n;
+    ca.nv = g.nv;
+    ca.drho = g.drho;
+    Timed tm(p, FZW_K_CIC, 7 * field_bytes(g));
+    launch_cic_adjoint(ca, g.nc, s);
+  }
+  // ALPT adjoint: D = sum_j (-i k_j / k^2) rfft(dPsi_j)
+  {
+    zf(g, g.psi, &sp[0], 3, s);
+    Pass py;
+    py.in(sp[0], true).in(sp[1], true).in(sp[2], true);
+    py.a.A[0][0] = spec_const(1.f);
+    py.a.A[1][1] = spec(0.f, -1.f, Y, NONE, NONE, NONE);
+    py.a.A[1][2] = spec(0.f, -1.f, Z, NONE, NONE, NONE);
+    py.out(sp[0], false).out(sp[1], false);
+    py.a.B[0][0] = spec_const(1.f);
+    py.a.B[1][1] = spec_const(1.f);
+    run_pass(g, Y, py, 2, s);
+    Pass ps;
+    ps.in(sp[0], true).in(sp[1], true);
+    ps.a.A[0][0] = spec(0.f, -1.f, X, NONE, TAB_INVK2, NONE);
+    ps.a.A[0][1] = spec(1.f, 0.f, NONE, NONE, TAB_INVK2, NONE);
+    ps.out(sp[2], true).out(sp[3], true).out(sp[4], false);
+    ps.a.B[0][0] = spec((float)(3.0 / 7.0) * d1 * d1 * invn3, 0.f, NONE, NONE, TAB_K, NONE);
+    ps.a.B[1][0] = spec(-invn3, 0.f, NONE, NONE, TAB_1MK, NONE);
+    ps.a.B[2][0] = spec(d1, 0.f, NONE, NONE, TAB_H, TAB_K);   // direct d nu_k (times N^3)
+    run_pass(g, X, ps, 1, s);
+    pure_pass(g, Y, true, &sp[2], 2, s);
+    float* dst[2] = {g.s2, g.dsc};
+    zi(g, &sp[2], dst, 2, s);
+  }
+  // LPT pointwise adjoint (d phi in place over phi)
+  {
+    LptArgs la{};
+    for (int c = 0; c < 6; ++c) {
+      la.phi[c] = g.phi[c];
+      la.dphi[c] = g.phi[c];
+    }
+    la.s2 = g.s2;
+    la.dsc = g.dsc;
+    la.d1 = d1;
+    la.tau = (float)p->cosmo.tau_sc;
+    la.n = (long long)g.nc * g.nv;
+    Timed tm(p, FZW_K_LPT, 14 * field_bytes(g));
+    launch_lpt_bwd(la, s);
+  }
+  // d nu_k = h / k^2 sum_ij k_i k_j rfft(d phi_ij) + direct ALPT term
+  {
+    zf(g, g.phi, &sp[5], 6, s);
+    Pass py;
+    for (int i = 0; i < 6; ++i) py.in(sp[5 + i], true);
+    py.a.A[0][0] = spec_const(1.f);
+    py.a.A[1][3] = spec(1.f, 0.f, Y, NONE, NONE, NONE);
+    py.a.A[1][4] = spec(1.f, 0.f, Z, NONE, NONE, NONE);
+    py.a.A[2][1] = spec(1.f, 0.f, Y, Y, NONE, NONE);
+    py.a.A[2][2] = spec(1.f, 0.f, Z, Z, NONE, NONE);
+    py.a.A[2][5] = spec(1.f, 0.f, Y, Z, NONE, NONE);
+    for (int o = 0; o < 3; ++o) {
+      py.out(sp[5 + o], false);
+      py.a.B[o][o] = spec_const(1.f);
+    }
+    run_pass(g, Y, py, 3, s);
+    Pass ps;
+    ps.in(sp[5], true).in(sp[6], true).in(sp[7], true).in(sp[4], false);
+    ps.a.A[0][0] = spec(invn3, 0.f, X, X, TAB_H, TAB_INVK2);
+    ps.a.A[0][1] = spec(invn3, 0.f, X, NONE, TAB_H, TAB_INVK2);
+    ps.a.A[0][2] = spec(invn3, 0.f, NONE, NONE, TAB_H, TAB_INVK2);
+    ps.a.A[0][3] = spec_const(invn3);
+    ps.out(sp[0], true);
+    ps.a.B[0][0] = spec_const(1.f);
+    run_pass(g, X, ps, 1, s);
+    pure_pass(g, Y, true, &sp[0], 1, s);
+    float* dst[1] = {dnu};
+    zi(g, &sp[0], dst, 1, s);
+  }
+}
+
+void check_ready(fzw_plan* p) {
+  for (int c = 0; c < p->n_chains; ++c)
+    if (!p->counts_set[c]) throw Error(FZW_E_STATE, "counts of chain " + std::to_string(c) + " not set");
+}
+
+void forward_all(fzw_plan* p, const float* nu, const float* bias, float* nbar, double* logl) {
+  t_plan = p;
+  for (auto& g : p->groups) forward_group(p, g, nu + p->chain_off[g.c0], bias, nbar, logl);
+}
+
+void value_and_grad_all(fzw_plan* p, const float* nu, const float* bias, double* logl, float* dnu, float* dbias) {
+  t_plan = p;
+  for (auto& g : p->groups) {
+    forward_group(p, g, nu + p->chain_off[g.c0], bias, nullptr, logl);
+    adjoint_group(p, g, bias, dnu + p->chain_off[g.c0], dbias);
+  }
+}
+
+template <class F>
+fzw_status guarded(F&& f) {
+  try {
+    f();
+    return FZW_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return FZW_E_HIP;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return FZW_E_HIP;
+  }
+}
+
+void free_plan(fzw_plan* p) {
+  for (auto& kv : p->graphs) {
+    (void)hipGraphExecDestroy(kv.second.e);
+    (void)hipGraphDestroy(kv.second.g);
+  }
+  if (p->ev_in) (void)hipEventDestroy(p->ev_in);
+  if (p->ev_out) (void)hipEventDestroy(p->ev_out);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  for (void* a : p->allocs) (void)hipFree(a);
+  for (auto e : p->evpool) (void)hipEventDestroy(e);
+  delete p;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* fzw_last_error(void) { return g_last_error.c_str(); }
+
+fzw_status fzw_plan_create(fzw_plan** out, int n_chains, const int* mesh_n, const double* box_l,
+                           const fzw_cosmo* cosmo, const fzw_web* web, void* stream) {
+  if (!out || !mesh_n || !box_l || !cosmo || !web || n_chains <= 0) {
+    g_last_error = "fzw_plan_create: null argument or n_chains <= 0";
+    return FZW_E_ARG;
+  }
+  *out = nullptr;
+  auto* p = new fzw_plan();
+  fzw_status st = guarded([&] {
+    if (web->n_webs < 1 || web->n_webs > 2) throw Error(FZW_E_ARG, "n_webs must be 1 or 2");
+    if (cosmo->rsd_axis < -1 || cosmo->rsd_axis > 2) throw Error(FZW_E_ARG, "rsd_axis must be -1..2");
+    if (!(cosmo->x_floor > 0)) throw Error(FZW_E_ARG, "x_floor must be > 0");
+    p->n_chains = n_chains;
+    p->cosmo = *cosmo;
+    p->web = *web;
+    p->W = web->n_webs;
+    p->R = p->W == 1 ? 4 : 16;
+    p->stream = static_cast<hipStream_t>(stream);
+    p->user_stream = p->stream;
+    p->amp = power_amplitude(*cosmo);
+    long long off = 0;
+    for (int c = 0; c < n_chains; ++c) {
+      if (!supported_n(mesh_n[c]))
+        throw Error(FZW_E_SIZE, "unsupported mesh size " + std::to_string(mesh_n[c]) +
+                                    " (supported: 16, 32, 64, 96, 128, 256, 512)");
+      if (!(box_l[c] > 0)) throw Error(FZW_E_ARG, "box_l must be > 0");
+      p->chain_off.push_back(off);
+      const long long nv = (long long)mesh_n[c] * mesh_n[c] * mesh_n[c];
+      off += nv;
+      if (!p->groups.empty() && p->groups.back().n == mesh_n[c] && p->groups.back().box == box_l[c]) {
+        p->groups.back().nc++;
+      } else {
+        Group g;
+        g.n = mesh_n[c];
+        g.box = box_l[c];
+        g.c0 = c;
+        g.nc = 1;
+        g.nv = nv;
+        g.P = spectrum_pitch(g.n);
+        g.ns = (long long)g.n * g.n * g.P;
+        g.nblk = (int)std::min<long long>((nv + 255) / 256, 2048);
+        p->groups.push_back(g);
+      }
+      p->chain_group.push_back((int)p->groups.size() - 1);
+    }
+    p->total_vox = off;
+    p->counts_set.assign(n_chains, false);
+    size_t part = 0;
+    for (auto& g : p->groups) {
+      build_tables(p, g);
+      alloc_group(p, g);
+      part = std::max(part, (size_t)g.nc * g.nblk * (size_t)std::max(2, p->R * 4));
+    }
+    part = std::max<size_t>(part, 512);
+    p->partial_elems = part;
+    p->partial = dalloc<double>(p, part);
+    p->counts = dalloc<uint16_t>(p, (size_t)off);
+    p->scal = dalloc<double>(p, (size_t)n_chains * kScalStride);
+    HIPCHK(hipMemset(p->scal, 0, (size_t)n_chains * kScalStride * sizeof(double)));
+    p->dnu_tmp = dalloc<float>(p, (size_t)off);
+    p->table_tmp = dalloc<float>(p, (size_t)n_chains * p->R * 4);
+    p->dtable_tmp = dalloc<float>(p, (size_t)n_chains * p->R * 4);
+    p->epartial = dalloc<double>(p, (size_t)n_chains * kEBlk);
+    p->tie = dalloc<int>(p, (size_t)p->R * 4);
+    p->mu = dalloc<double>(p, 64);
+    p->sigma = dalloc<double>(p, 64);
+    // default priority, non-blocking: the caller's stream may be the legacy
+    // default stream, which cannot be captured
+    HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming));
+    HIPCHK(hipDeviceSynchronize());
+  });
+  if (st != FZW_OK) {
+    free_plan(p);
+    return st;
+  }
+  *out = p;
+  return FZW_OK;
+}
+
+void fzw_plan_destroy(fzw_plan* plan) {
+  if (!plan) return;
+  (void)hipStreamSynchronize(plan->stream);
+  free_plan(plan);
+}
+
+fzw_status fzw_set_counts(fzw_plan* p, int chain, const uint16_t* counts) {
+  if (!p || !counts || chain < 0 || chain >= p->n_chains) {
+    g_last_error = "fzw_set_counts: bad argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    const Group& g = p->groups[p->chain_group[chain]];
+    uint16_t* dst = p->counts + p->chain_off[chain];
+    HIPCHK(hipMemcpyAsync(dst, counts, g.nv * sizeof(uint16_t), hipMemcpyDeviceToDevice, p->stream));
+    launch_count_consts(dst, g.nv, p->partial, 256, p->scal + (size_t)chain * kScalStride, p->stream);
+    HIPCHK(hipStreamSynchronize(p->stream));
+    double ntr = 0;
+    HIPCHK(hipMemcpy(&ntr, p->scal + (size_t)chain * kScalStride + kScalNtr, sizeof(double), hipMemcpyDeviceToHost));
+    if (!(ntr > 0)) throw Error(FZW_E_ARG, "counts of chain " + std::to_string(chain) + " sum to zero");
+    p->counts_set[chain] = true;
+  });
+}
+
+fzw_status fzw_forward(fzw_plan* p, const float* nu, const float* bias, float* nbar, double* logl) {
+  if (!p || !nu || !bias || !logl) {
+    g_last_error = "fzw_forward: null argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    check_ready(p);
+    forward_all(p, nu, bias, nbar, logl);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+fzw_status fzw_value_and_grad(fzw_plan* p, const float* nu, const float* bias, double* logl, float* dnu,
+                              float* dbias) {
+  if (!p || !nu || !bias || !logl || !dnu || !dbias) {
+    g_last_error = "fzw_value_and_grad: null argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    check_ready(p);
+    value_and_grad_all(p, nu, bias, logl, dnu, dbias);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+fzw_status fzw_set_sampling(fzw_plan* p, const int* tie, int n_free, const double* prior_mu,
+                            const double* prior_sigma) {
+  if (!p || !tie || n_free < 0 || n_free > 64 || (n_free > 0 && (!prior_mu || !prior_sigma))) {
+    g_last_error = "fzw_set_sampling: bad argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    for (int e = 0; e < p->R * 4; ++e)
+      if (tie[e] < -1 || tie[e] >= n_free) throw Error(FZW_E_ARG, "tie entry out of range");
+    for (int f = 0; f < n_free; ++f)
+      if (!(prior_sigma[f] > 0)) throw Error(FZW_E_ARG, "prior_sigma must be > 0");
+    HIPCHK(hipMemcpy(p->tie, tie, sizeof(int) * p->R * 4, hipMemcpyHostToDevice));
+    if (n_free > 0) {
+      HIPCHK(hipMemcpy(p->mu, prior_mu, sizeof(double) * n_free, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(p->sigma, prior_sigma, sizeof(double) * n_free, hipMemcpyHostToDevice));
+    }
+    p->nfree = n_free;
+    for (auto& kv : p->graphs) {
+      (void)hipGraphExecDestroy(kv.second.e);
+      (void)hipGraphDestroy(kv.second.g);
+    }
+    p->graphs.clear();
+  });
+}
+
+static void enqueue_trajectory(fzw_plan* p, float* nu, float* u, float* p_nu, float* p_u, const float* base,
+                               const float* minv_nu, const float* minv_u, const float* step, int n_steps,
+                               double* h_start, double* h_end) {
+  hipStream_t s = p->stream;
+  ParamArgs pa{};
+  pa.u = u;
+  pa.pu = p_u;
+  pa.minv_u = minv_u;
+  pa.mu = p->mu;
+  pa.sigma = p->sigma;
+  pa.tie = p->tie;
+  pa.base = base;
+  pa.table = p->table_tmp;
+  pa.dtable = p->dtable_tmp;
+  pa.step = step;
+  pa.scal = p->scal;
+  pa.epartial = p->epartial;
+  pa.ne = p->R * 4;
+  pa.nfree = p->nfree;
+  const int C = p->n_chains;
+  auto grad = [&] {
+    launch_params(pa, C, 0, 0.f, kEBlk, nullptr, s);
+    value_and_grad_all(p, nu, p->table_tmp, nullptr, p->dnu_tmp, p->dtable_tmp);
+  };
+  auto leap = [&](const Group& g) {
+    LeapArgs la{};
+    la.q = nu + p->chain_off[g.c0];
+    la.p = p_nu + p->chain_off[g.c0];
+    la.g = p->dnu_tmp + p->chain_off[g.c0];
+    la.minv = minv_nu + p->chain_off[g.c0];
+    la.step = step;
+    la.chain0 = g.c0;
+    la.nv = g.nv;
+    la.partial = p->epartial + (size_t)g.c0 * kEBlk;
+    return la;
+  };
+  auto hamiltonian = [&](double* h) {
+    for (auto& g : p->groups) launch_energy(leap(g), g.nc, kEBlk, s);
+    launch_params(pa, C, 3, 0.f, kEBlk, h, s);
+  };
+  grad();
+  hamiltonian(h_start);
+  for (int it = 0; it < n_steps; ++it) {
+    for (auto& g : p->groups) launch_kick(leap(g), g.nc, 0.5f, s);
+    launch_params(pa, C, 1, 0.5f, kEBlk, nullptr, s);
+    for (auto& g : p->groups) launch_drift(leap(g), g.nc, s);
+    launch_params(pa, C, 2, 0.f, kEBlk, nullptr, s);
+    grad();
+    for (auto& g : p->groups) launch_kick(leap(g), g.nc, 0.5f, s);
+    launch_params(pa, C, 1, 0.5f, kEBlk, nullptr, s);
+  }
+  hamiltonian(h_end);
+}
+
+fzw_status fzw_leapfrog(fzw_plan* p, float* nu, float* u, float* p_nu, float* p_u, const float* bias_base,
+                        const float* minv_nu, const float* minv_u, const float* step, int n_steps,
+                        double* h_start, double* h_end) {
+  if (!p || !nu || !p_nu || !bias_base || !minv_nu || !step || !h_start || !h_end || n_steps < 0) {
+    g_last_error = "fzw_leapfrog: bad argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    check_ready(p);
+    if (p->nfree < 0) throw Error(FZW_E_STATE, "fzw_set_sampling not called");
+    if (p->nfree > 0 && (!u || !p_u || !minv_u)) throw Error(FZW_E_ARG, "u, p_u, minv_u required");
+    std::vector<uintptr_t> key = {(uintptr_t)nu, (uintptr_t)u, (uintptr_t)p_nu, (uintptr_t)p_u,
+                                  (uintptr_t)bias_base, (uintptr_t)minv_nu, (uintptr_t)minv_u,
+                                  (uintptr_t)step, (uintptr_t)n_steps, (uintptr_t)h_start, (uintptr_t)h_end};
+    auto it = p->graphs.find(key);
+    // order the private stream after the caller's work
+    HIPCHK(hipEventRecord(p->ev_in, p->user_stream));
+    HIPCHK(hipStreamWaitEvent(p->cap_stream, p->ev_in, 0));
+    if (it == p->graphs.end()) {
+      fzw_plan::GraphEntry ge{};
+      HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+      p->stream = p->cap_stream;
+      const bool timing = p->timing;   // no event records inside the graph
+      p->timing = false;
+      try {
+        enqueue_trajectory(p, nu, u, p_nu, p_u, bias_base, minv_nu, minv_u, step, n_steps, h_start, h_end);
+      } catch (...) {
+        p->stream = p->user_stream;
+        p->timing = timing;
+        hipGraph_t dummy;
+        (void)hipStreamEndCapture(p->cap_stream, &dummy);
+        (void)hipGetLastError();
+        throw;
+      }
+      p->stream = p->user_stream;
+      p->timing = timing;
+      HIPCHK(hipStreamEndCapture(p->cap_stream, &ge.g));
+      HIPCHK(hipGraphInstantiate(&ge.e, ge.g, nullptr, nullptr, 0));
+      it = p->graphs.emplace(key, ge).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second.e, p->cap_stream));
+    // and the caller's stream after the trajectory
+    HIPCHK(hipEventRecord(p->ev_out, p->cap_stream));
+    HIPCHK(hipStreamWaitEvent(p->user_stream, p->ev_out, 0));
+  });
+}
+
+fzw_status fzw_get_field(fzw_plan* p, int chain, int field, float* out) {
+  if (!p || !out || chain < 0 || chain >= p->n_chains || field < 0 || field >= 6 + 6 * p->W) {
+    g_last_error = "fzw_get_field: bad argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    const Group& g = p->groups[p->chain_group[chain]];
+    const long long o = (long long)(chain - g.c0) * g.nv;
+    const size_t bytes = g.nv * sizeof(float);
+    const float* src = nullptr;
+    if (field == 0) {
+      // delta_L is the trace of the first-order Hessian
+      launch_trace3(g.phi[0] + o, g.phi[1] + o, g.phi[2] + o, out, g.nv, p->stream);
+      return;
+    }
+    if (field <= 3) src = g.psi[field - 1] + o;
+    else if (field == 4) src = g.rho + o;
+    else if (field == 5) src = g.logf + o;
+    else src = g.tens[field - 6] + o;
+    HIPCHK(hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToDevice, p->stream));
+  });
+}
+
+static fzw_status fft_common(fzw_plan* p, int n, int batch, const void* in, void* out, bool r2c) {
+  if (!p || !in || !out || batch <= 0) {
+    g_last_error = "fzw_fft: bad argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    const Group* gp = nullptr;
+    for (auto& g : p->groups)
+      if (g.n == n) gp = &g;
+    if (!gp) throw Error(FZW_E_SIZE, "mesh size not in plan");
+    Group g = *gp;
+    g.nc = 1;
+    t_plan = p;
+    const long long m1 = n / 2 + 1;
+    for (int b = 0; b < batch; ++b) {
+      if (r2c) {
+        float* src[1] = {const_cast<float*>(static_cast<const float*>(in)) + (size_t)b * g.nv};
+        zf(g, src, &g.spec[0], 1, p->stream);
+        pure_pass(g, Y, false, &g.spec[0], 1, p->stream);
+        pure_pass(g, X, false, &g.spec[0], 1, p->stream);
+        launch_spec_repack(g.spec[0], static_cast<float2*>(out) + (size_t)b * n * n * m1, n, g.P, (int)m1,
+                           (long long)n * n, p->stream);
+      } else {
+        launch_spec_repack(static_cast<const float2*>(in) + (size_t)b * n * n * m1, g.spec[0], n, (int)m1, g.P,
+                           (long long)n * n, p->stream);
+        pure_pass(g, X, true, &g.spec[0], 1, p->stream);
+        pure_pass(g, Y, true, &g.spec[0], 1, p->stream);
+        float* dst[1] = {static_cast<float*>(out) + (size_t)b * g.nv};
+        zi(g, &g.spec[0], dst, 1, p->stream);
+      }
+    }
+    HIPCHK(hipGetLastError());
+  });
+}
+
+fzw_status fzw_fft_r2c(fzw_plan* p, int n, int batch, const float* in, void* out_complex) {
+  return fft_common(p, n, batch, in, out_complex, true);
+}
+fzw_status fzw_fft_c2r(fzw_plan* p, int n, int batch, const void* in_complex, float* out) {
+  return fft_common(p, n, batch, in_complex, out, false);
+}
+
+fzw_status fzw_timing_enable(fzw_plan* p, int on) {
+  if (!p) {
+    g_last_error = "fzw_timing_enable: null plan";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    HIPCHK(hipStreamSynchronize(p->stream));
+    p->timing = on != 0;
+    p->recs.clear();
+    p->evused = 0;
+  });
+}
+
+fzw_status fzw_timing_read(fzw_plan* p, int klass, double* total_ms, long long* launches, double* bytes) {
+  if (!p || klass < 0 || klass >= FZW_K_COUNT || !total_ms || !launches || !bytes) {
+    g_last_error = "fzw_timing_read: bad argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    HIPCHK(hipStreamSynchronize(p->stream));
+    double ms = 0, b = 0;
+    long long n = 0;
+    for (auto& r : p->recs) {
+      if (r.klass != klass) continue;
+      float e = 0;
+      HIPCHK(hipEventElapsedTime(&e, r.a, r.b));
+      ms += e;
+      b += r.bytes;
+      ++n;
+    }
+    *total_ms = ms;
+    *launches = n;
+    *bytes = b;
+  });
+}
+
+size_t fzw_chain_offset(const fzw_plan* p, int chain) {
+  if (!p || chain < 0 || chain >= p->n_chains) return 0;
+  return (size_t)p->chain_off[chain];
+}
+int fzw_n_regions(const fzw_plan* p) { return p ? p->R : 0; }
+size_t fzw_workspace_bytes(const fzw_plan* p) { return p ? p->ws_bytes : 0; }
+
+}  // extern "C"

@@ -1,0 +1,273 @@
+"""Python binding of libfzw.so (the gfx950 HIP library behind include/fzw.h).
+
+Argument marshalling only: every stage of the forward model, its adjoint and
+the leapfrog runs in the library's HIP kernels.  PyTorch provides the device
+memory (tensors on cuda) and the stream (the current torch stream at plan
+creation).  There is no CPU fallback: without the built library or a GPU the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfzw.so")
+_lib = None
+
+WEB_PHI, WEB_DELTA = 0, 1
+KERNEL_CLASSES = ("zpass", "xypass", "cic", "lpt", "voxel_fwd", "likelihood", "voxel_bwd")
+
+
+class FzwError(RuntimeError):
+    pass
+
+
+class CCosmo(ctypes.Structure):
+    _fields_ = [("omega_m", ctypes.c_double), ("h", ctypes.c_double), ("sigma8", ctypes.c_double),
+                ("n_s", ctypes.c_double), ("d1", ctypes.c_double), ("f_growth", ctypes.c_double),
+                ("r_s", ctypes.c_double), ("rsd_axis", ctypes.c_int), ("tau_sc", ctypes.c_double),
+                ("x_floor", ctypes.c_double)]
+
+
+class CWeb(ctypes.Structure):
+    _fields_ = [("n_webs", ctypes.c_int), ("kind", ctypes.c_int * 2), ("smooth_r", ctypes.c_double * 2),
+                ("ell", ctypes.c_double * 2), ("steepness", ctypes.c_double), ("lambda_th", ctypes.c_double)]
+
+
+def load_library(path: str = _LIB_PATH):
+    """Load libfzw.so and declare its signatures (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FzwError("libfzw.so is not built at %s; run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    lib.fzw_plan_create.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(i), ctypes.POINTER(d),
+                                    ctypes.POINTER(CCosmo), ctypes.POINTER(CWeb), vp]
+    lib.fzw_plan_destroy.argtypes = [vp]
+    lib.fzw_plan_destroy.restype = None
+    lib.fzw_set_counts.argtypes = [vp, i, vp]
+    lib.fzw_forward.argtypes = [vp, vp, vp, vp, vp]
+    lib.fzw_value_and_grad.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.fzw_set_sampling.argtypes = [vp, ctypes.POINTER(i), i, ctypes.POINTER(d), ctypes.POINTER(d)]
+    lib.fzw_leapfrog.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i, vp, vp]
+    lib.fzw_get_field.argtypes = [vp, i, i, vp]
+    lib.fzw_fft_r2c.argtypes = [vp, i, i, vp, vp]
+    lib.fzw_fft_c2r.argtypes = [vp, i, i, vp, vp]
+    lib.fzw_timing_enable.argtypes = [vp, i]
+    lib.fzw_timing_enable.restype = ctypes.c_int
+    lib.fzw_timing_read.argtypes = [vp, i, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(d)]
+    lib.fzw_timing_read.restype = ctypes.c_int
+    lib.fzw_chain_offset.argtypes = [vp, i]
+    lib.fzw_chain_offset.restype = sz
+    lib.fzw_n_regions.argtypes = [vp]
+    lib.fzw_workspace_bytes.argtypes = [vp]
+    lib.fzw_workspace_bytes.restype = sz
+    lib.fzw_last_error.restype = ctypes.c_char_p
+    for name in ("fzw_plan_create", "fzw_set_counts", "fzw_forward", "fzw_value_and_grad",
+                 "fzw_set_sampling", "fzw_leapfrog", "fzw_get_field", "fzw_fft_r2c", "fzw_fft_c2r"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        msg = _lib.fzw_last_error().decode() if _lib is not None else ""
+        raise FzwError("%s failed with status %d: %s" % (what, status, msg))
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise FzwError("tensor must live on the GPU")
+    if dtype is not None and t.dtype != dtype:
+        raise FzwError("expected %s, got %s" % (dtype, t.dtype))
+    if not t.is_contiguous():
+        raise FzwError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class CosmoParams:
+    omega_m: float = 0.31
+    h: float = 0.68
+    sigma8: float = 0.81
+    n_s: float = 0.96
+    d1: float = 1.0
+    f_growth: float = 0.31 ** 0.55
+    r_s: float = 4.0
+    rsd_axis: int = -1
+    tau_sc: float = 0.0
+    x_floor: float = 1e-6
+
+    def c(self) -> CCosmo:
+        return CCosmo(self.omega_m, self.h, self.sigma8, self.n_s, self.d1, self.f_growth, self.r_s,
+                      self.rsd_axis, self.tau_sc, self.x_floor)
+
+
+@dataclass
+class WebParams:
+    kinds: Sequence[int] = (WEB_PHI,)
+    smooth_r: Sequence[float] = (0.0,)
+    ell: Sequence[float] = (0.0,)
+    steepness: float = 20.0
+    lambda_th: float = 0.1
+
+    def c(self) -> CWeb:
+        n = len(self.kinds)
+        w = CWeb()
+        w.n_webs = n
+        for k in range(n):
+            w.kind[k] = int(self.kinds[k])
+            w.smooth_r[k] = float(self.smooth_r[k])
+            w.ell[k] = float(self.ell[k])
+        w.steepness = self.steepness
+        w.lambda_th = self.lambda_th
+        return w
+
+
+class Plan:
+    """A set of chains (meshes) sharing cosmology and web settings."""
+
+    def __init__(self, mesh_n: Sequence[int], box_l: Sequence[float], cosmo: CosmoParams, web: WebParams,
+                 device: int = 0):
+        lib = load_library()
+        self.device = torch.device("cuda", device)
+        self.mesh_n = [int(n) for n in mesh_n]
+        self.box_l = [float(b) for b in box_l]
+        self.n_chains = len(self.mesh_n)
+        self.cosmo, self.web = cosmo, web
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            h = ctypes.c_void_p()
+            arr_n = (ctypes.c_int * self.n_chains)(*self.mesh_n)
+            arr_l = (ctypes.c_double * self.n_chains)(*self.box_l)
+            cc, cw = cosmo.c(), web.c()
+            _check(lib.fzw_plan_create(ctypes.byref(h), self.n_chains, arr_n, arr_l, ctypes.byref(cc),
+                                       ctypes.byref(cw), ctypes.c_void_p(self.stream.cuda_stream)),
+                   "fzw_plan_create")
+        self._h = h
+        self.n_regions = lib.fzw_n_regions(h)
+        self.offsets = [int(lib.fzw_chain_offset(h, c)) for c in range(self.n_chains)]
+        self.total_voxels = self.offsets[-1] + self.mesh_n[-1] ** 3
+        self.nfree = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.fzw_plan_destroy(h)
+            self._h = None
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(_lib.fzw_workspace_bytes(self._h))
+
+    def chain_view(self, packed: torch.Tensor, c: int) -> torch.Tensor:
+        n = self.mesh_n[c]
+        o = self.offsets[c]
+        return packed[o:o + n ** 3].view(n, n, n)
+
+    def set_counts(self, chain: int, counts: torch.Tensor):
+        """counts: uint16 data on the GPU (any int16/uint16 tensor with N^3 entries)."""
+        if counts.dtype not in (torch.int16, torch.uint16):
+            raise FzwError("counts must be 16-bit")
+        _check(_lib.fzw_set_counts(self._h, chain, _ptr(counts.contiguous())), "fzw_set_counts")
+
+    def forward(self, nu: torch.Tensor, bias: torch.Tensor, want_nbar: bool = False):
+        logl = torch.empty(self.n_chains, dtype=torch.float64, device=self.device)
+        nbar = torch.empty_like(nu) if want_nbar else None
+        _check(_lib.fzw_forward(self._h, _ptr(nu, torch.float32), _ptr(bias, torch.float32), _ptr(nbar),
+                                _ptr(logl)), "fzw_forward")
+        return (logl, nbar) if want_nbar else logl
+
+    def value_and_grad(self, nu: torch.Tensor, bias: torch.Tensor, out=None):
+        if out is None:
+            out = (torch.empty(self.n_chains, dtype=torch.float64, device=self.device),
+                   torch.empty_like(nu), torch.empty_like(bias))
+        logl, dnu, dbias = out
+        _check(_lib.fzw_value_and_grad(self._h, _ptr(nu, torch.float32), _ptr(bias, torch.float32),
+                                       _ptr(logl, torch.float64), _ptr(dnu, torch.float32),
+                                       _ptr(dbias, torch.float32)), "fzw_value_and_grad")
+        return logl, dnu, dbias
+
+    def set_sampling(self, tie: Sequence[int], mu: Sequence[float], sigma: Sequence[float]):
+        nf = len(mu)
+        arr_t = (ctypes.c_int * len(tie))(*[int(x) for x in tie])
+        arr_m = (ctypes.c_double * max(nf, 1))(*[float(x) for x in mu])
+        arr_s = (ctypes.c_double * max(nf, 1))(*[float(x) for x in sigma])
+        _check(_lib.fzw_set_sampling(self._h, arr_t, nf, arr_m, arr_s), "fzw_set_sampling")
+        self.nfree = nf
+
+    def leapfrog(self, nu, u, p_nu, p_u, bias_base, minv_nu, minv_u, step, n_steps, h_start=None, h_end=None):
+        if h_start is None:
+            h_start = torch.empty(self.n_chains, dtype=torch.float64, device=self.device)
+        if h_end is None:
+            h_end = torch.empty(self.n_chains, dtype=torch.float64, device=self.device)
+        _check(_lib.fzw_leapfrog(self._h, _ptr(nu, torch.float32), _ptr(u), _ptr(p_nu, torch.float32), _ptr(p_u),
+                                 _ptr(bias_base, torch.float32), _ptr(minv_nu, torch.float32), _ptr(minv_u),
+                                 _ptr(step, torch.float32), int(n_steps), _ptr(h_start, torch.float64),
+                                 _ptr(h_end, torch.float64)), "fzw_leapfrog")
+        return h_start, h_end
+
+    def timing(self, on: bool):
+        """Bracket every later launch with HIP events (per kernel class)."""
+        _check(_lib.fzw_timing_enable(self._h, 1 if on else 0), "fzw_timing_enable")
+
+    def timing_report(self):
+        """{class: (total_ms, launches, algorithmic_bytes)} since timing(True)."""
+        out = {}
+        for k, name in enumerate(KERNEL_CLASSES):
+            ms, n, b = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+            _check(_lib.fzw_timing_read(self._h, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)),
+                   "fzw_timing_read")
+            out[name] = (ms.value, n.value, b.value)
+        return out
+
+    def get_field(self, chain: int, field_id: int) -> torch.Tensor:
+        n = self.mesh_n[chain]
+        out = torch.empty((n, n, n), dtype=torch.float32, device=self.device)
+        _check(_lib.fzw_get_field(self._h, chain, field_id, _ptr(out)), "fzw_get_field")
+        return out
+
+    def fft_r2c(self, x: torch.Tensor) -> torch.Tensor:
+        n = x.shape[-1]
+        b = x.numel() // n ** 3
+        out = torch.empty((b, n, n, n // 2 + 1), dtype=torch.complex64, device=self.device)
+        _check(_lib.fzw_fft_r2c(self._h, n, b, _ptr(x.contiguous(), torch.float32), _ptr(out)), "fzw_fft_r2c")
+        return out
+
+    def fft_c2r(self, x: torch.Tensor) -> torch.Tensor:
+        n = x.shape[-2]
+        b = x.numel() // (n * n * (n // 2 + 1))
+        out = torch.empty((b, n, n, n), dtype=torch.float32, device=self.device)
+        _check(_lib.fzw_fft_c2r(self._h, n, b, _ptr(x.contiguous(), torch.complex64), _ptr(out)), "fzw_fft_c2r")
+        return out
+
+
+class LogLikelihood(torch.autograd.Function):
+    """logL(nu, bias) per chain with the library's hand-written adjoint as backward."""
+
+    @staticmethod
+    def forward(ctx, nu, bias, plan: Plan):
+        logl, dnu, dbias = plan.value_and_grad(nu.detach().contiguous(), bias.detach().contiguous())
+        ctx.save_for_backward(dnu, dbias)
+        ctx.plan = plan
+        return logl
+
+    @staticmethod
+    def backward(ctx, g):
+        dnu, dbias = ctx.saved_tensors
+        plan = ctx.plan
+        gn = torch.empty_like(dnu)
+        for c in range(plan.n_chains):
+            o, n = plan.offsets[c], plan.mesh_n[c] ** 3
+            gn[o:o + n] = dnu[o:o + n] * g[c].to(dnu.dtype)
+        gb = dbias * g.to(dbias.dtype).view(-1, *([1] * (dbias.dim() - 1)))
+        return gn, gb, None

@@ -23,9 +23,9 @@ def oracle_model(w, chain=0):
 
 
 @functools.lru_cache(maxsize=16)
-def mock_case(name, n=None, tau_sc=0.0, chain=0):
+def mock_case(name, n=None, tau_sc=None, chain=0):
     """(workload, oracle model, truth nu, eval nu, counts) for a workload."""
-    kw = {"tau_sc": tau_sc} if tau_sc else {}
+    kw = {"tau_sc": tau_sc} if tau_sc is not None else {}
     w = workload_at(name, n, **kw)
     ch = w.chains[chain]
     m = oracle_model(w, chain)

@@ -21,6 +21,7 @@ GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def _model(n=16, box=125.0, **kw):
+    kw.setdefault("tau_sc", 0.0)   # the exact spherical-collapse hinge
     cos = fi.Cosmo(**{k: v for k, v in kw.items() if k in fi.Cosmo.__dataclass_fields__})
     web = fi.Web(**{k: v for k, v in kw.items() if k in fi.Web.__dataclass_fields__})
     ch = fi.Chain(n, box, fi.four_class_table(), 1.0, (9, n))
