@@ -383,40 +383,66 @@ __device__ __forceinline__ void any_orthogonal(const float* a, float* v) {
   v[2] = c[2] * s;
 }
 
+__device__ __forceinline__ void sym_mul(const float t[6], const float* x, float* y) {
+  y[0] = t[0] * x[0] + t[3] * x[1] + t[4] * x[2];
+  y[1] = t[3] * x[0] + t[1] * x[1] + t[5] * x[2];
+  y[2] = t[4] * x[0] + t[5] * x[1] + t[2] * x[2];
+}
+__device__ __forceinline__ float dot3(const float* a, const float* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Eigen-decomposition of a symmetric 3x3 tensor that stays accurate for
+// nearly equal eigenvalues: the trigonometric solution only picks the
+// eigenvalue farthest from the other two; its eigenvector (a cross product of
+// two rows of T - l I, well conditioned because that eigenvalue is isolated)
+// is taken first, and the remaining pair is the exact Jacobi rotation of T
+// restricted to the orthogonal plane.  Returns eigenvalues descending and the
+// unit eigenvectors v1 (largest) and v3 (smallest).
+__device__ __forceinline__ void eig3_robust(const float t[6], float lam[3], float v1[3], float v3[3]) {
+  float q, p;
+  float l0[3];
+  eig3_values(t, l0, q, p);
+  v1[0] = 1.f; v1[1] = 0.f; v1[2] = 0.f;
+  v3[0] = 0.f; v3[1] = 0.f; v3[2] = 1.f;
+  lam[0] = l0[0]; lam[1] = l0[1]; lam[2] = l0[2];
+  if (!(p > 0.f)) return;
+  const bool top = (l0[0] - l0[1]) >= (l0[1] - l0[2]);
+  float v[3];
+  if (!eig3_vector(t, top ? l0[0] : l0[2], (p * p) * (p * p) * 81.f, v)) return;
+  float u[3], w[3], tu[3], tw[3], tv[3];
+  any_orthogonal(v, u);
+  cross3(v, u, w);
+  sym_mul(t, u, tu);
+  sym_mul(t, w, tw);
+  sym_mul(t, v, tv);
+  const float a = dot3(u, tu), b = dot3(u, tw), c = dot3(w, tw);
+  float cs = 1.f, sn = 0.f, tt = 0.f;
+  if (b != 0.f) {
+    const float tau = (c - a) / (2.f * b);
+    tt = copysignf(1.f, tau) / (fabsf(tau) + sqrtf(1.f + tau * tau));
+    cs = rsqrtf(1.f + tt * tt);
+    sn = tt * cs;
+  }
+  // pairs (value, vector): (v.Tv, v), (a - t b, cs u - sn w), (c + t b, sn u + cs w)
+  float L[3] = {dot3(v, tv), a - tt * b, c + tt * b};
+  float V[3][3] = {{v[0], v[1], v[2]},
+                   {cs * u[0] - sn * w[0], cs * u[1] - sn * w[1], cs * u[2] - sn * w[2]},
+                   {sn * u[0] + cs * w[0], sn * u[1] + cs * w[1], sn * u[2] + cs * w[2]}};
+  int i0 = 0, i1 = 1, i2 = 2;   // sort descending by index
+  if (L[i0] < L[i1]) { int x = i0; i0 = i1; i1 = x; }
+  if (L[i1] < L[i2]) { int x = i1; i1 = i2; i2 = x; }
+  if (L[i0] < L[i1]) { int x = i0; i0 = i1; i1 = x; }
+  lam[0] = L[i0]; lam[1] = L[i1]; lam[2] = L[i2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    v1[k] = i0 == 0 ? V[0][k] : (i0 == 1 ? V[1][k] : V[2][k]);
+    v3[k] = i2 == 0 ? V[0][k] : (i2 == 1 ? V[1][k] : V[2][k]);
+  }
+}
+
 // Gradient of a function of the eigenvalues with respect to the tensor:
 // G = sum_n g_n v_n v_n^T = g2 I + (g1 - g2) v1 v1^T + (g3 - g2) v3 v3^T.
 // Returned as cotangents of the 6 stored components (off-diagonals doubled).
-__device__ __forceinline__ void eig3_grad(const float t[6], const float lam[3], float p, const float g[3],
-                                          float out[6]) {
-  float v1[3] = {1.f, 0.f, 0.f}, v3[3] = {0.f, 0.f, 1.f};
-  if (p > 0.f) {
-    const float scale4 = (p * p) * (p * p) * 81.f;
-    const bool first_top = (lam[0] - lam[1]) >= (lam[1] - lam[2]);
-    float* va = first_top ? v1 : v3;
-    float* vb = first_top ? v3 : v1;
-    const float la = first_top ? lam[0] : lam[2];
-    const float lb = first_top ? lam[2] : lam[0];
-    float tmp[3];
-    if (eig3_vector(t, la, scale4, tmp)) {
-      va[0] = tmp[0]; va[1] = tmp[1]; va[2] = tmp[2];
-    } else {
-      va[0] = first_top ? 1.f : 0.f; va[1] = 0.f; va[2] = first_top ? 0.f : 1.f;
-    }
-    bool okb = eig3_vector(t, lb, scale4, tmp);
-    if (okb) {
-      const float d = tmp[0] * va[0] + tmp[1] * va[1] + tmp[2] * va[2];
-      tmp[0] -= d * va[0];
-      tmp[1] -= d * va[1];
-      tmp[2] -= d * va[2];
-      const float nn = tmp[0] * tmp[0] + tmp[1] * tmp[1] + tmp[2] * tmp[2];
-      okb = nn > 1e-12f;
-      if (okb) {
-        const float s = rsqrtf(nn);
-        vb[0] = tmp[0] * s; vb[1] = tmp[1] * s; vb[2] = tmp[2] * s;
-      }
-    }
-    if (!okb) any_orthogonal(va, vb);
-  }
+__device__ __forceinline__ void eig3_grad(const float v1[3], const float v3[3], const float g[3], float out[6]) {
   const float a1 = g[0] - g[1], a3 = g[2] - g[1];
   out[0] = g[1] + a1 * v1[0] * v1[0] + a3 * v3[0] * v3[0];
   out[1] = g[1] + a1 * v1[1] * v1[1] + a3 * v3[1] * v3[1];
@@ -453,34 +479,22 @@ __device__ __forceinline__ double digamma_d(double x) {
          ix2 * (1.0 / 12 - ix2 * (1.0 / 120 - ix2 * (1.0 / 252 - ix2 * (1.0 / 240 - ix2 * (1.0 / 132)))));
 }
 
-// sum_{m<n} ln(beta+m) = lnGamma(n+beta) - lnGamma(beta) and its beta
-// derivative sum_{m<n} 1/(beta+m), in float64: counts above 64 are rare and
-// take the special functions out of line.
-__device__ __noinline__ void nb_gamma_big(int n, double beta, double& lg, double& dg) {
-  lg = lgamma((double)n + beta) - lgamma(beta);
-  dg = digamma_d((double)n + beta) - digamma_d(beta);
+// Counts above 64 are rare: their lnGamma(n+beta) - lnGamma(beta) and
+// psi(n+beta) - psi(beta) use float64 special functions out of line (below
+// that the finite sums over m < n are used).
+__device__ __noinline__ float nb_lgamma_big(int n, float beta) {
+  const double b = beta;
+  return (float)(lgamma((double)n + b) - lgamma(b));
 }
-
-__device__ __forceinline__ void nb_gamma_terms(int n, double beta, double& lg, double& dg) {
-  if (n <= 64) {
-    double s = 0.0, d = 0.0;
-    for (int m = 0; m < n; ++m) {
-      const double bm = beta + (double)m;
-      s += log(bm);
-      d += 1.0 / bm;
-    }
-    lg = s;
-    dg = d;
-  } else {
-    nb_gamma_big(n, beta, lg, dg);
-  }
+__device__ __noinline__ double nb_digamma_big(int n, double beta) {
+  return digamma_d((double)n + beta) - digamma_d(beta);
 }
 
 // ---------------------------------------------------------- per-voxel fused
 template <int W>
 struct VoxelCore {
   static constexpr int R = W == 1 ? 4 : 16;
-  float lam[W][3], pw[W], wgt[W][3], pm[W][4], preg[R];
+  float lam[W][3], v1[W][3], v3[W][3], wgt[W][3], pm[W][4], preg[R];
   float theta[4];
   float x, lnx, ellr, u, logf;
   float t6[W][6];
@@ -490,8 +504,7 @@ struct VoxelCore {
     for (int w = 0; w < W; ++w) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) t6[w][c] = a.tens[w * 6 + c][i];
-      float q;
-      eig3_values(t6[w], lam[w], q, pw[w]);
+      eig3_robust(t6[w], lam[w], v1[w], v3[w]);
       web_memberships(lam[w], a.steep, a.lam_th, wgt[w], pm[w]);
     }
     if (W == 1) {
@@ -539,27 +552,30 @@ __global__ __launch_bounds__(256) void voxel_fwd_kernel(VoxelArgs a) {
 }
 
 // Likelihood pass: needs ln C = ln N_tr - ln sum f from the reduced partials.
-// The per-voxel negative-binomial terms are evaluated in float64 (a few
-// operations per voxel): their sum is what drives the Metropolis decision.
+// Per-voxel terms in FP32 (accurate library functions), sums in FP64.
 __global__ __launch_bounds__(256) void likelihood_kernel(LikeArgs a) {
   __shared__ double red[4];
   const long long c = blockIdx.y;
   const long long nv = a.nv;
-  const double lnc = a.scal[c * kScalStride + kScalLnC];
+  const float lnc = (float)a.scal[c * kScalStride + kScalLnC];
   double sl = 0.0, sg = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x) {
-    const double lf = a.logf[c * nv + i];
-    const double beta = a.beta[c * nv + i];
+    const float lf = a.logf[c * nv + i];
+    const float beta = a.beta[c * nv + i];
     const int n = a.counts[c * nv + i];
-    const double lnb = lnc + lf;
-    const double nb = exp(lnb);
-    const double l1p = log1p(nb / beta);
-    double lg, dg;
-    nb_gamma_terms(n, beta, lg, dg);
-    const double fn = (double)n;
-    sl += lg - (beta + fn) * l1p + fn * (lnb - log(beta));
-    sg += beta * (fn - nb) / (beta + nb);
-    if (a.nbar) a.nbar[c * nv + i] = (float)nb;
+    const float lnb = lnc + lf;
+    const float nb = expf(lnb);
+    const float l1p = log1pf(nb / beta);
+    float lg = 0.f;
+    if (n <= 64) {
+      for (int m = 0; m < n; ++m) lg += logf(beta + (float)m);
+    } else {
+      lg = nb_lgamma_big(n, beta);
+    }
+    const float fn = (float)n;
+    sl += (double)(lg - (beta + fn) * l1p + fn * (lnb - logf(beta)));
+    sg += (double)(beta * (fn - nb) / (beta + nb));
+    if (a.nbar) a.nbar[c * nv + i] = nb;
   }
   const double s1 = block_sum(sl, red);
   const double s2 = block_sum(sg, red);
@@ -569,11 +585,19 @@ __global__ __launch_bounds__(256) void likelihood_kernel(LikeArgs a) {
   }
 }
 
+// Per-voxel adjoint of bias, memberships and web tensors.  The bias-table
+// gradient sum_i p_r,i dtheta_c,i is reduced through LDS: every pass of the
+// block stores p (float) and dtheta (float64) of its 256 voxels, then thread t
+// sums entry t % NE over a fixed subset of those voxels (fixed order, so the
+// result is reproducible).
 template <int W>
 __global__ __launch_bounds__(256) void voxel_bwd_kernel(VoxelArgs a) {
   constexpr int R = W == 1 ? 4 : 16;
   constexpr int NE = R * 4;
-  __shared__ double wpart[4][NE];
+  constexpr int G = 256 / NE;          // voxel groups per entry
+  __shared__ float sp[R][256];
+  __shared__ double sd[4][256];
+  __shared__ double sacc[256];
   const long long c = blockIdx.y;
   const long long nv = a.nv;
   const float* tab = a.table + c * NE;
@@ -582,39 +606,38 @@ __global__ __launch_bounds__(256) void voxel_bwd_kernel(VoxelArgs a) {
   const double* sc = a.scal + c * kScalStride;
   const double lnc = sc[kScalLnC];
   const double gcoef = sc[kScalG] / sc[kScalNtr];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  double acc = 0.0;   // lane e accumulates table-gradient entry e of its wave
+  const int t = threadIdx.x;
+  const int my_e = t % NE, my_g = t / NE;
+  double acc = 0.0;
   for (long long i0 = blockIdx.x * (long long)blockDim.x; i0 < nv; i0 += (long long)gridDim.x * blockDim.x) {
-    const long long i = i0 + threadIdx.x;
+    const long long i = i0 + t;
     double dth[4] = {0.0, 0.0, 0.0, 0.0};
-    float preg[R];
     if (i < nv) {
       VoxelCore<W> v;
       const float rho = a.rho[c * nv + i];
       v.run(b, tab, i, rho);
 #pragma unroll
-      for (int r = 0; r < R; ++r) preg[r] = v.preg[r];
-      // scalar bias / likelihood chain in float64 (its table sums cancel to
-      // ~1% at the data's own parameters, and the beta derivative cancels per
-      // voxel)
+      for (int r = 0; r < R; ++r) sp[r][t] = v.preg[r];
+      // float64 where the sums cancel: n-bar, the NB terms and d/d beta
       const int n = a.counts[c * nv + i];
       const double fn = (double)n;
-      const double al = v.theta[0], ep = v.theta[1], rt = v.theta[2], beta = v.theta[3];
-      const double xd = (double)v.x;
-      const double lnx = log(xd);
-      const double ellr = lnx - log(rt);
-      const double u = exp(ep * ellr);
-      const double nb = exp(lnc + al * lnx - u);
+      const double beta = v.theta[3];
+      const double nb = exp(lnc + (double)v.logf);
       const double l1p = log1p(nb / beta);
-      double lg, dg;
-      nb_gamma_terms(n, beta, lg, dg);
+      double dg = 0.0;
+      if (n <= 64) {
+        for (int m = 0; m < n; ++m) dg += 1.0 / (beta + (double)m);
+      } else {
+        dg = nb_digamma_big(n, beta);
+      }
       const double ghat = beta * (fn - nb) / (beta + nb);
       const double af = ghat - gcoef * nb;                      // f dlogL/df
+      const double lnx = v.lnx, u = v.u, ellr = v.ellr;
       dth[0] = af * lnx;
       dth[1] = -af * u * ellr;
-      dth[2] = af * u * ep / rt;
+      dth[2] = af * u * (double)v.theta[1] / (double)v.theta[2];
       dth[3] = dg - l1p + (nb - fn) / (beta + nb);
-      const double dxv = af * (al - ep * u) / xd;
+      const double dxv = af * ((double)v.theta[0] - (double)v.theta[1] * u) / (double)v.x;
       a.drho[c * nv + i] = rho > a.x_floor ? (float)dxv : 0.f;
       float dp[R];
 #pragma unroll
@@ -645,26 +668,35 @@ __global__ __launch_bounds__(256) void voxel_bwd_kernel(VoxelArgs a) {
 #pragma unroll
         for (int m = 0; m < 3; ++m) gl[m] = dw[m] * a.steep * v.wgt[w][m] * (1.f - v.wgt[w][m]);
         float gt[6];
-        eig3_grad(v.t6[w], v.lam[w], v.pw[w], gl, gt);
+        eig3_grad(v.v1[w], v.v3[w], gl, gt);
 #pragma unroll
         for (int k = 0; k < 6; ++k) a.dtens[w * 6 + k][c * nv + i] = gt[k];
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < R; ++r) preg[r] = 0.f;
+      for (int r = 0; r < R; ++r) sp[r][t] = 0.f;
     }
 #pragma unroll
-    for (int e = 0; e < NE; ++e) {
-      const double s = wave_sum((double)preg[e / 4] * dth[e % 4]);
-      if (lane == e) acc += s;
+    for (int k = 0; k < 4; ++k) sd[k][t] = dth[k];
+    __syncthreads();
+    {
+      const int r = my_e >> 2, k = my_e & 3;
+      double s = 0.0;
+#pragma unroll 8
+      for (int q = 0; q < NE; ++q) {
+        const int vx = my_g + G * q;
+        s += (double)sp[r][vx] * sd[k][vx];
+      }
+      acc += s;
     }
+    __syncthreads();
   }
-  if (lane < NE) wpart[wid][lane] = acc;
+  sacc[t] = acc;
   __syncthreads();
-  if (threadIdx.x < NE) {
+  if (t < NE) {
     double s = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += wpart[w][threadIdx.x];
-    a.partial[(c * gridDim.x + blockIdx.x) * NE + threadIdx.x] = s;
+    for (int g = 0; g < G; ++g) s += sacc[g * NE + t];
+    a.partial[(c * gridDim.x + blockIdx.x) * NE + t] = s;
   }
 }
 
@@ -697,11 +729,13 @@ __global__ void finalize_kernel(FinalArgs a) {
       if (a.logl) a.logl[c] = logl;
     }
   } else {
+    // one block-wide fixed-order sum per table entry
     const int ne = a.ne;
-    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    for (int e = 0; e < ne; ++e) {
       double s = 0.0;
-      for (int i = 0; i < a.nblk; ++i) s += a.partial[(c * a.nblk + i) * ne + e];
-      a.dtable[c * ne + e] = (float)s;
+      for (int i = threadIdx.x; i < a.nblk; i += blockDim.x) s += a.partial[(c * a.nblk + i) * ne + e];
+      s = block_sum(s, red);
+      if (threadIdx.x == 0) a.dtable[c * ne + e] = (float)s;
     }
   }
 }
