@@ -127,6 +127,15 @@ def main():
         print("#   %-11s %7.3f ms/step %6.1f launches  %8.1f us/launch  %7.1f GB/s" % (
             k, v["ms_per_step"], v["launches_per_step"], v["avg_launch_us"], v["GBps"]), file=sys.stderr)
 
+    # the alternative CIC deposit (fixed-point atomics), same results
+    plan.set_cic_method("atomic")
+    for _ in range(max(1, args.warmup)):
+        plan.value_and_grad(nu, bias, out)
+    ga, _ = _time_steps(plan, nu, bias, out, args.steps, torch)
+    plan.set_cic_method("sorted")
+    cic_atomic = {"ms_per_step": 1e3 * ga / args.steps, "value": args.steps / ga, "unit": "grads/s"}
+    print("# with the atomic CIC deposit: %.3f ms/step" % cic_atomic["ms_per_step"], file=sys.stderr, flush=True)
+
     # batched: several identical 256^3 chains in one plan
     batched = None
     if args.batch > 1:
@@ -169,6 +178,7 @@ def main():
                                "1 chain, forward+adjoint" % (w.name, n, ch.box, w.web.n_webs, w.n_regions),
                    "mesh": n, "box": ch.box, "chains": 1},
         "batched": batched,
+        "cic_atomic": cic_atomic,
         "algorithmic_GBps_all_kernels": total_alg / (ms_per_step * 1e6),
         "hbm_frac_algorithmic": total_alg / (ms_per_step * 1e6) / HBM_PEAK_GBS,
         "kernel_classes": classes,

@@ -152,6 +152,17 @@ fzw_status fzw_get_field(fzw_plan* plan, int chain, int field, float* out);
 fzw_status fzw_fft_r2c(fzw_plan* plan, int n, int batch, const float* in, void* out_complex);
 fzw_status fzw_fft_c2r(fzw_plan* plan, int n, int batch, const void* in_complex, float* out);
 
+/* Cloud-in-cell deposit method.  Both give bit-identical densities: every
+ * weight is rounded to a multiple of 2^-32 and summed exactly in 64-bit
+ * integers, so neither depends on the order of particles.
+ *   FZW_CIC_SORTED (default): counting sort of the particles by destination
+ *     cell, then each node gathers the weights of the particles in its 8
+ *     neighbouring buckets (no atomics on the densities).
+ *   FZW_CIC_ATOMIC: each particle adds its 8 weights with 64-bit integer
+ *     atomics into a fixed-point accumulator. */
+enum { FZW_CIC_SORTED = 0, FZW_CIC_ATOMIC = 1 };
+fzw_status fzw_set_cic_method(fzw_plan* plan, int method);
+
 /* Kernel classes for per-launch timing. */
 enum {
   FZW_K_ZPASS = 0,     /* z-axis real<->complex FFT passes */

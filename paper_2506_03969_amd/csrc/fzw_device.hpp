@@ -171,6 +171,131 @@ __device__ __forceinline__ void fft_lines(float2* lds, const float2* tw) {
   }
 }
 
+// ------------------------------------------------ register (four-step) DFTs
+// Compile-time trigonometry for the twiddles inside register DFTs.
+constexpr double kPiD = 3.14159265358979323846264338327950288;
+constexpr double cx_sin(double x) {
+  while (x > kPiD) x -= 2.0 * kPiD;
+  while (x < -kPiD) x += 2.0 * kPiD;
+  double term = x, sum = x;
+  for (int i = 1; i < 40; ++i) {
+    term *= -x * x / ((2.0 * i) * (2.0 * i + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double cx_cos(double x) { return cx_sin(x + 0.5 * kPiD); }
+
+template <int N>
+struct CTw {   // exp(-2 pi i k / N)
+  float re[N], im[N];
+  constexpr CTw() : re(), im() {
+    for (int k = 0; k < N; ++k) {
+      re[k] = (float)cx_cos(2.0 * kPiD * k / N);
+      im[k] = (float)(-cx_sin(2.0 * kPiD * k / N));
+    }
+  }
+};
+
+template <int N, bool INV>
+__device__ __forceinline__ float2 ctw(int k) {
+  constexpr CTw<N> t{};
+  return make_float2(t.re[k], INV ? -t.im[k] : t.im[k]);
+}
+
+// Natural-order DFT of N values held in registers (N = 2, 4, 8, 16, 32).
+template <int N, bool INV>
+__device__ __forceinline__ void dft_reg(float2* v) {
+  if constexpr (N == 2) dft2<INV>(v);
+  else if constexpr (N == 4) dft4<INV>(v);
+  else if constexpr (N == 8) dft8<INV>(v);
+  else {
+    // N = 4 * B: length-B DFTs over stride-4 subsequences, twiddles, length-4 DFTs
+    constexpr int B = N / 4;
+    float2 s[4][B];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) s[a][b] = v[a + 4 * b];
+      dft_reg<B, INV>(s[a]);
+#pragma unroll
+      for (int k = 1; k < B; ++k)
+        if (a > 0) s[a][k] = cmul(s[a][k], ctw<N, INV>(a * k));
+    }
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      float2 t[4] = {s[0][k], s[1][k], s[2][k], s[3][k]};
+      dft4<INV>(t);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) v[B * a + k] = t[a];
+    }
+  }
+}
+
+// Factorisation N = N1 * N2 (N2 = m N1) of the register four-step transforms.
+template <int N> struct F4;
+template <> struct F4<8>   { static constexpr int N1 = 2, N2 = 4; };
+template <> struct F4<16>  { static constexpr int N1 = 4, N2 = 4; };
+template <> struct F4<32>  { static constexpr int N1 = 4, N2 = 8; };
+template <> struct F4<64>  { static constexpr int N1 = 8, N2 = 8; };
+template <> struct F4<128> { static constexpr int N1 = 8, N2 = 16; };
+template <> struct F4<256> { static constexpr int N1 = 16, N2 = 16; };
+
+// LDS needed per line by the exchanges (rows padded by one element).
+template <int N>
+__host__ __device__ constexpr int f4_lds() { return N + F4<N>::N2; }
+
+// Layout A: thread j (of N1 per line) holds elements j + N1 q, q < N2.
+// Layout B: thread j holds elements N2 k1 + (j + N1 u), at register u N1 + k1.
+// Forward transform A -> B through one LDS exchange (`lline` is this line's
+// LDS slice of N values, `tw` = exp(-2 pi i k / N)); all threads of the
+// workgroup must call it (it synchronises).
+template <int N, bool INV_UNUSED = false>
+__device__ __forceinline__ void fwd_A_to_B(float2* v, float2* lline, int j, const float2* tw) {
+  constexpr int N1 = F4<N>::N1, N2 = F4<N>::N2, M = N2 / N1;
+  dft_reg<N2, false>(v);
+#pragma unroll
+  for (int k2 = 1; k2 < N2; ++k2) v[k2] = cmul(v[k2], tw[j * k2]);
+#pragma unroll
+  for (int k2 = 0; k2 < N2; ++k2) lline[j * (N2 + 1) + k2] = v[k2];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < M; ++u) {
+    float2 b[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) b[n1] = lline[n1 * (N2 + 1) + j + N1 * u];
+    dft_reg<N1, false>(b);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) v[u * N1 + k1] = b[k1];
+  }
+  __syncthreads();
+}
+
+// Inverse transform B -> A (unnormalised), one LDS exchange.
+template <int N>
+__device__ __forceinline__ void inv_B_to_A(float2* v, float2* lline, int j, const float2* tw) {
+  constexpr int N1 = F4<N>::N1, N2 = F4<N>::N2, M = N2 / N1;
+#pragma unroll
+  for (int u = 0; u < M; ++u) {
+    const int k2 = j + N1 * u;
+    float2 z[N1];
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) z[k1] = v[u * N1 + k1];
+    dft_reg<N1, true>(z);
+#pragma unroll
+    for (int q = 0; q < N1; ++q) {
+      float2 w = tw[k2 * q];
+      w.y = -w.y;
+      lline[k2 * (N1 + 1) + q] = q ? cmul(z[q], w) : z[q];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int n = 0; n < N2; ++n) v[n] = lline[n * (N1 + 1) + j];
+  dft_reg<N2, true>(v);
+  __syncthreads();
+}
+
 // ------------------------------------------------------ spectral multipliers
 // Signed frequency index of position i on an axis of length n.
 __device__ __forceinline__ int freq_index(int i, int n) { return i <= (n - 1) / 2 ? i : i - n; }

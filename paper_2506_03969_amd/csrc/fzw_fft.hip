@@ -236,18 +236,239 @@ __global__ __launch_bounds__(kThreadsXY) void xy_pass_kernel(PassArgs a, const f
   }
 }
 
+// ============================================ register four-step variants
+// The same passes with the transform done as N = N1 N2: each thread loads its
+// N2 strided elements straight into registers, runs a length-N2 DFT there,
+// one LDS exchange regroups the data, and a length-N1 DFT finishes it in
+// registers (layout B).  The inverse starts from layout B, so a fused
+// forward / mix / inverse pass touches LDS only twice.
+
+template <int N>
+__host__ __device__ constexpr int z4_lines() {
+  return (kTile / (N / 2)) > N * N ? N * N : kTile / (N / 2);
+}
+
+template <int N>
+__global__ __launch_bounds__(z4_lines<N>() * F4<N / 2>::N1) void zpass4_r2c_kernel(ZArgs a, const float2* __restrict__ tw_half,
+                                                                               const float2* __restrict__ tw_full) {
+  constexpr int M = N / 2;
+  constexpr int N1 = F4<M>::N1, N2 = F4<M>::N2, MU = N2 / N1;
+  constexpr int L = z4_lines<N>();
+  constexpr int NT = L * N1;
+  constexpr int LSZ = f4_lds<M>();
+  constexpr int P = pitch_c<N>();
+  __shared__ float2 lds[L * LSZ];
+  __shared__ float2 twh[M];
+  __shared__ float2 twf[N];
+  const int t = threadIdx.x;
+  const int j = t % N1, l = t / N1;
+  const int arr = blockIdx.z % a.narr;
+  const long long chain = blockIdx.z / a.narr;
+  const float2* in = reinterpret_cast<const float2*>(a.in[arr]) + chain * (a.in_chain_stride / 2);
+  float2* out = reinterpret_cast<float2*>(a.out[arr]) + chain * a.out_chain_stride;
+  const long long line = (long long)blockIdx.x * L + l;
+  for (int i = t; i < M; i += NT) twh[i] = tw_half[i];
+  for (int i = t; i < N; i += NT) twf[i] = tw_full[i];
+  float2 v[N2];
+  const float2* src = in + line * M;
+#pragma unroll
+  for (int q = 0; q < N2; ++q) v[q] = src[j + N1 * q];
+  __syncthreads();
+  float2* ll = lds + l * LSZ;
+  fwd_A_to_B<M>(v, ll, j, twh);
+  // natural order into LDS for the real-to-complex unpacking
+#pragma unroll
+  for (int u = 0; u < MU; ++u)
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) ll[N2 * k1 + j + N1 * u] = v[u * N1 + k1];
+  __syncthreads();
+  float2* row = out + line * P;
+  for (int k = j; k <= M; k += N1) {
+    const float2 zk = ll[k == M ? 0 : k];
+    const float2 zm = ll[k == 0 ? 0 : M - k];
+    const float2 A = cadd(zk, cconj(zm));
+    const float2 B = csub(zk, cconj(zm));
+    const float2 wB = cmul(twf[k], B);
+    row[k] = make_float2(0.5f * (A.x + wB.y), 0.5f * (A.y - wB.x));
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(z4_lines<N>() * F4<N / 2>::N1) void zpass4_c2r_kernel(ZArgs a, const float2* __restrict__ tw_half,
+                                                                               const float2* __restrict__ tw_full) {
+  constexpr int M = N / 2;
+  constexpr int N1 = F4<M>::N1, N2 = F4<M>::N2, MU = N2 / N1;
+  constexpr int L = z4_lines<N>();
+  constexpr int NT = L * N1;
+  constexpr int LSZ = f4_lds<M>();
+  constexpr int P = pitch_c<N>();
+  __shared__ float2 lds[L * LSZ];
+  __shared__ float2 twh[M];
+  __shared__ float2 twf[N];
+  const int t = threadIdx.x;
+  const int j = t % N1, l = t / N1;
+  const int arr = blockIdx.z % a.narr;
+  const long long chain = blockIdx.z / a.narr;
+  const float2* in = reinterpret_cast<const float2*>(a.in[arr]) + chain * a.in_chain_stride;
+  float2* out = reinterpret_cast<float2*>(a.out[arr]) + chain * (a.out_chain_stride / 2);
+  const long long line = (long long)blockIdx.x * L + l;
+  for (int i = t; i < M; i += NT) twh[i] = tw_half[i];
+  for (int i = t; i < N; i += NT) twf[i] = tw_full[i];
+  __syncthreads();
+  const float2* row = in + line * P;
+  float2 v[N2];
+#pragma unroll
+  for (int u = 0; u < MU; ++u) {
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+      const int k = N2 * k1 + j + N1 * u;
+      float2 xk = row[k];
+      float2 xm = row[M - k];
+      if (k == 0) {
+        xk.y = 0.f;
+        xm.y = 0.f;
+      }
+      const float2 A = cadd(xk, cconj(xm));
+      const float2 B = csub(xk, cconj(xm));
+      const float2 cB = cmul(cconj(twf[k]), B);
+      v[u * N1 + k1] = make_float2(A.x - cB.y, A.y + cB.x);
+    }
+  }
+  inv_B_to_A<M>(v, lds + l * LSZ, j, twh);
+  float2* dst = out + line * M;
+#pragma unroll
+  for (int q = 0; q < N2; ++q) dst[j + N1 * q] = v[q];
+}
+
+// Strided x / y pass, four-step variant.  Tile: C columns x N rows; thread t
+// owns column t % C and four-step index j = t / C.
+template <int N>
+__host__ __device__ constexpr int xy4_cols() {
+  return kTile / N > 256 ? 256 : kTile / N;
+}
+
+// Used for single-mix passes (NMID = 1), where three workgroups per CU fit in
+// registers without spilling; multi-mix passes use the Stockham kernel.
+template <int N, int AXIS, int NMID>
+__global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1, 3) void xy4_pass_kernel(PassArgs a, const float2* __restrict__ twg) {
+  constexpr int N1 = F4<N>::N1, N2 = F4<N>::N2, MU = N2 / N1;
+  constexpr int M = N / 2;
+  constexpr int P = pitch_c<N>();
+  constexpr int C = xy4_cols<N>();
+  constexpr int NT = C * N1;
+  constexpr int LSZ = f4_lds<N>() + 1;
+  __shared__ float2 lds[C * LSZ];
+  __shared__ float2 tw[N];
+  const int t = threadIdx.x;
+  const int c = t % C, j = t / C;
+  const int c0 = blockIdx.x * C;
+  const int b = blockIdx.y;
+  const long long chain = blockIdx.z;
+  const long long rstride = AXIS == 0 ? (long long)N * P : (long long)P;
+  const bool valid = (c0 + c) <= M;
+  const long long base = chain * a.chain_stride + (AXIS == 0 ? (long long)b * P : (long long)b * N * P) + c0 + c;
+  for (int i = t; i < N; i += NT) tw[i] = twg[i];
+  const int nb = freq_index(b, N);
+  const int nz = valid ? c0 + c : 0;
+  const int nyq = N / 2;
+  float2* lcol = lds + c * LSZ;
+  // rows held in layout B (register u N1 + k1)
+  auto rowB = [&](int e) { return N2 * (e % N1) + j + N1 * (e / N1); };
+
+  float2 mid[NMID][N2];
+#pragma unroll
+  for (int m = 0; m < NMID; ++m)
+#pragma unroll
+    for (int e = 0; e < N2; ++e) mid[m][e] = make_float2(0.f, 0.f);
+  __syncthreads();
+
+  for (int i = 0; i < a.nin; ++i) {
+    const float2* src = a.in[i] + base;
+    float2 val[N2];
+    if (a.in_fft & (1u << i)) {
+#pragma unroll
+      for (int q = 0; q < N2; ++q) val[q] = valid ? src[(j + N1 * q) * rstride] : make_float2(0.f, 0.f);
+      fwd_A_to_B<N>(val, lcol, j, tw);
+    } else {
+#pragma unroll
+      for (int e = 0; e < N2; ++e) val[e] = valid ? src[rowB(e) * rstride] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int m = 0; m < NMID; ++m) {
+      const SpecOp op = a.A[m][i];
+      if (op.re != 0.f || op.im != 0.f) {
+#pragma unroll
+        for (int e = 0; e < N2; ++e) {
+          KVec kv;
+          const int nr = freq_index(rowB(e), N);
+          kv.n[0] = AXIS == 0 ? nr : 0;
+          kv.n[1] = AXIS == 0 ? nb : nr;
+          kv.n[2] = nz;
+          kv.n2 = kv.n[0] * kv.n[0] + kv.n[1] * kv.n[1] + nz * nz;
+          mid[m][e] = cadd(mid[m][e], cmul(spec_eval(op, kv, a.kf, nyq, a.tabs, a.tab_stride), val[e]));
+        }
+      }
+    }
+  }
+
+  for (int o = 0; o < a.nout; ++o) {
+    float2 val[N2];
+#pragma unroll
+    for (int e = 0; e < N2; ++e) val[e] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int m = 0; m < NMID; ++m) {
+      const SpecOp op = a.B[o][m];
+      if (op.re != 0.f || op.im != 0.f) {
+#pragma unroll
+        for (int e = 0; e < N2; ++e) {
+          KVec kv;
+          const int nr = freq_index(rowB(e), N);
+          kv.n[0] = AXIS == 0 ? nr : 0;
+          kv.n[1] = AXIS == 0 ? nb : nr;
+          kv.n[2] = nz;
+          kv.n2 = kv.n[0] * kv.n[0] + kv.n[1] * kv.n[1] + nz * nz;
+          val[e] = cadd(val[e], cmul(spec_eval(op, kv, a.kf, nyq, a.tabs, a.tab_stride), mid[m][e]));
+        }
+      }
+    }
+    float2* dst = a.out[o] + base;
+    if (a.out_fft & (1u << o)) {
+      inv_B_to_A<N>(val, lcol, j, tw);
+      if (valid) {
+#pragma unroll
+        for (int q = 0; q < N2; ++q) dst[(j + N1 * q) * rstride] = val[q];
+      }
+    } else if (valid) {
+#pragma unroll
+      for (int e = 0; e < N2; ++e) dst[rowB(e) * rstride] = val[e];
+    }
+  }
+}
+
 // ------------------------------------------------------------- launchers
 template <int N>
 static void zr2c(const ZArgs& za, long long chains, const float2* twh, const float2* twf, hipStream_t s) {
-  constexpr int L = zlines<N>();
-  dim3 grid((N * N) / L, 1, (unsigned)(za.narr * chains));
-  hipLaunchKernelGGL(zpass_r2c_kernel<N>, grid, dim3(kThreads), 0, s, za, twh, twf);
+  if constexpr (N == 96) {
+    constexpr int L = zlines<N>();
+    dim3 grid((N * N) / L, 1, (unsigned)(za.narr * chains));
+    hipLaunchKernelGGL(zpass_r2c_kernel<N>, grid, dim3(kThreads), 0, s, za, twh, twf);
+  } else {
+    constexpr int L = z4_lines<N>();
+    dim3 grid((N * N) / L, 1, (unsigned)(za.narr * chains));
+    hipLaunchKernelGGL(zpass4_r2c_kernel<N>, grid, dim3(L * F4<N / 2>::N1), 0, s, za, twh, twf);
+  }
 }
 template <int N>
 static void zc2r(const ZArgs& za, long long chains, const float2* twh, const float2* twf, hipStream_t s) {
-  constexpr int L = zlines<N>();
-  dim3 grid((N * N) / L, 1, (unsigned)(za.narr * chains));
-  hipLaunchKernelGGL(zpass_c2r_kernel<N>, grid, dim3(kThreads), 0, s, za, twh, twf);
+  if constexpr (N == 96) {
+    constexpr int L = zlines<N>();
+    dim3 grid((N * N) / L, 1, (unsigned)(za.narr * chains));
+    hipLaunchKernelGGL(zpass_c2r_kernel<N>, grid, dim3(kThreads), 0, s, za, twh, twf);
+  } else {
+    constexpr int L = z4_lines<N>();
+    dim3 grid((N * N) / L, 1, (unsigned)(za.narr * chains));
+    hipLaunchKernelGGL(zpass4_c2r_kernel<N>, grid, dim3(L * F4<N / 2>::N1), 0, s, za, twh, twf);
+  }
 }
 
 #define FZW_DISPATCH_N(n, F, ...)                 \
@@ -291,7 +512,24 @@ void launch_zpass_c2r(int n, const float2* const* in, float* const* out, int nar
 }
 
 template <int N>
+static void xyp4(int axis, const PassArgs& a, int chains, const float2* tw, hipStream_t s) {
+  constexpr int C = xy4_cols<N>();
+  dim3 grid((N / 2 + 1 + C - 1) / C, N, chains);
+  dim3 block(C * F4<N>::N1);
+#define FZW_XY4(AX, NM) hipLaunchKernelGGL((xy4_pass_kernel<N, AX, NM>), grid, block, 0, s, a, tw)
+  if (axis == 0) FZW_XY4(0, 1);
+  else FZW_XY4(1, 1);
+#undef FZW_XY4
+}
+
+template <int N>
 static void xyp(int axis, const PassArgs& a, int chains, const float2* tw, hipStream_t s) {
+  if constexpr (N != 96 && N != 512) {
+    if (a.nmid == 1) {
+      xyp4<N>(axis, a, chains, tw, s);
+      return;
+    }
+  }
   constexpr int C = xycols<N>();
   dim3 grid((N / 2 + 1 + C - 1) / C, N, chains);
 #define FZW_XY(AX, NM) hipLaunchKernelGGL((xy_pass_kernel<N, AX, NM>), grid, dim3(kThreadsXY), 0, s, a, tw)

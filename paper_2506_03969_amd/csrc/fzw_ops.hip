@@ -295,6 +295,50 @@ __global__ void cic_adjoint_kernel(CicArgs a) {
   }
 }
 
+// Alternative deposit: every particle adds its 8 trilinear weights into a
+// 64-bit fixed-point accumulator with integer atomics (no return value); the
+// same FP32 weights and the same rounding to 2^-32 as the gather make the
+// result bit-identical to it, and integer addition makes it order-free.
+__global__ void cic_atomic_kernel(CicArgs a) {
+  const long long nv = a.nv;
+  const int n = a.n;
+  const long long c = blockIdx.y;
+  CicArgs b = a;
+  for (int d = 0; d < 3; ++d) b.psi[d] = a.psi[d] + c * nv;
+  unsigned long long* acc = a.acc + c * nv;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nv; p += (long long)gridDim.x * blockDim.x) {
+    int cx, cy, cz;
+    float tx, ty, tz;
+    cic_locate(b, p, n, cx, cy, cz, tx, ty, tz);
+    const int nx = cx + 1 == n ? 0 : cx + 1;
+    const int ny = cy + 1 == n ? 0 : cy + 1;
+    const int nz = cz + 1 == n ? 0 : cz + 1;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
+      const float w = (ox ? tx : 1.f - tx) * (oy ? ty : 1.f - ty) * (oz ? tz : 1.f - tz);
+      const long long q = ((long long)(ox ? nx : cx) * n + (oy ? ny : cy)) * n + (oz ? nz : cz);
+      atomicAdd(acc + q, (unsigned long long)__float2ll_rn(w * 4294967296.0f));
+    }
+  }
+}
+
+// rho from the accumulator; the accumulator is cleared for the next deposit.
+__global__ void cic_convert_kernel(CicArgs a, long long total) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+    const unsigned long long v = a.acc[i];
+    a.rho[i] = (float)((double)(long long)v * (1.0 / 4294967296.0));
+    a.acc[i] = 0ull;
+  }
+}
+
+void launch_cic_deposit_atomic(const CicArgs& a, int chains, hipStream_t s) {
+  dim3 gp(grid_for(a.nv, 256, 32768), chains);
+  hipLaunchKernelGGL(cic_atomic_kernel, gp, dim3(256), 0, s, a);
+  const long long total = a.nv * chains;
+  hipLaunchKernelGGL(cic_convert_kernel, dim3(grid_for(total, 256, 32768)), dim3(256), 0, s, a, total);
+}
+
 void launch_cic_deposit(const CicArgs& a, int chains, hipStream_t s) {
   const long long nv = a.nv;
   launch_fill_i32(a.count, nv * chains, 0, s);

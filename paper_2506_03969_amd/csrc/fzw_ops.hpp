@@ -27,6 +27,7 @@ struct CicArgs {
   int* bsum;             // [chains][nv/4096 rounded up]
   int2* keyslot;         // [chains][nv]
   float4* sorted;        // [chains][nv]
+  unsigned long long* acc;  // [chains][nv] fixed-point accumulator (atomic deposit), kept zero
   float* rho;            // [chains][nv]
   const float* drho;     // adjoint input
   float* dpsi[3];        // adjoint output
@@ -100,6 +101,7 @@ void launch_lpt_fwd(const LptArgs& a, hipStream_t s);
 void launch_lpt_bwd(const LptArgs& a, hipStream_t s);
 void launch_cic_deposit(const CicArgs& a, int chains, hipStream_t s);
 void launch_cic_adjoint(const CicArgs& a, int chains, hipStream_t s);
+void launch_cic_deposit_atomic(const CicArgs& a, int chains, hipStream_t s);
 void launch_voxel_fwd(int w, const VoxelArgs& a, int chains, int nblk, hipStream_t s);
 void launch_voxel_bwd(int w, const VoxelArgs& a, int chains, int nblk, hipStream_t s);
 void launch_likelihood(const LikeArgs& a, int chains, int nblk, hipStream_t s);

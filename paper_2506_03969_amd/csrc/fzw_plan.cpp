@@ -100,6 +100,7 @@ struct Group {
   int* bsum = nullptr;
   int2* keyslot = nullptr;
   float4* sorted = nullptr;
+  unsigned long long* acc = nullptr;
 };
 
 }  // namespace fzw
@@ -133,6 +134,7 @@ struct fzw_plan {
   double* mu = nullptr;
   double* sigma = nullptr;
   int nfree = -1;
+  int cic_method = FZW_CIC_SORTED;
   std::vector<void*> allocs;
   size_t ws_bytes = 0;
   struct GraphEntry {
@@ -268,6 +270,8 @@ void alloc_group(fzw_plan* p, Group& g) {
   g.bsum = dalloc<int>(p, (size_t)g.nc * ((g.nv + 4095) / 4096));
   g.keyslot = dalloc<int2>(p, nf);
   g.sorted = dalloc<float4>(p, nf);
+  g.acc = dalloc<unsigned long long>(p, nf);
+  HIPCHK(hipMemset(g.acc, 0, nf * sizeof(unsigned long long)));
 }
 
 // ------------------------------------------------------------- pass helpers
@@ -304,19 +308,74 @@ void run_pass(const Group& g, int axis, Pass& ps, int nmid, hipStream_t s) {
 }
 
 // pure forward or inverse transform of k arrays along an axis, in place
+// (one launch per array: every strided pass carries a single mix slot)
 void pure_pass(const Group& g, int axis, bool inverse, float2* const* arr, int k, hipStream_t s) {
-  int done = 0;
-  while (done < k) {
-    const int m = std::min(kMaxMid, k - done);
+  for (int i = 0; i < k; ++i) {
     Pass ps;
-    for (int i = 0; i < m; ++i) ps.in(arr[done + i], !inverse);
-    for (int i = 0; i < m; ++i) ps.out(arr[done + i], inverse);
-    for (int i = 0; i < m; ++i) {
-      ps.a.A[i][i] = spec_const(1.f);
-      ps.a.B[i][i] = spec_const(1.f);
-    }
-    run_pass(g, axis, ps, m, s);
-    done += m;
+    ps.in(arr[i], !inverse).out(arr[i], inverse);
+    ps.a.A[0][0] = spec_const(1.f);
+    ps.a.B[0][0] = spec_const(1.f);
+    run_pass(g, axis, ps, 1, s);
+  }
+}
+
+// Inverse y pass from the three x-pass outputs (factors k_x^2, k_x, 1 of a
+// Hessian k_i k_j m(k)) to the six tensor components xx, yy, zz, xy, xz, yz.
+void hessian_yi(const Group& g, float2* a2, float2* a1, float2* a0, float2* const* out6, hipStream_t s) {
+  {
+    Pass p2;
+    p2.in(a2, false).out(out6[0], true);
+    p2.a.A[0][0] = spec_const(1.f);
+    p2.a.B[0][0] = spec_const(1.f);
+    run_pass(g, 1, p2, 1, s);
+  }
+  {
+    Pass p1;
+    p1.in(a1, false).out(out6[3], true).out(out6[4], true);
+    p1.a.A[0][0] = spec_const(1.f);
+    p1.a.B[0][0] = spec(1.f, 0.f, 1, -1, -1, -1);   // k_y  -> xy
+    p1.a.B[1][0] = spec(1.f, 0.f, 2, -1, -1, -1);   // k_z  -> xz
+    run_pass(g, 1, p1, 1, s);
+  }
+  {
+    Pass p0;
+    p0.in(a0, false).out(out6[1], true).out(out6[2], true).out(out6[5], true);
+    p0.a.A[0][0] = spec_const(1.f);
+    p0.a.B[0][0] = spec(1.f, 0.f, 1, 1, -1, -1);    // k_y^2 -> yy
+    p0.a.B[1][0] = spec(1.f, 0.f, 2, 2, -1, -1);    // k_z^2 -> zz
+    p0.a.B[2][0] = spec(1.f, 0.f, 1, 2, -1, -1);    // k_y k_z -> yz
+    run_pass(g, 1, p0, 1, s);
+  }
+}
+
+// Adjoint of hessian_yi: forward y pass of the six cotangent components
+// (xx, yy, zz, xy, xz, yz) grouped by their x factor into three arrays.
+void hessian_yf(const Group& g, float2* const* in6, float2* g2, float2* g1, float2* g0, hipStream_t s) {
+  // Order matters when the outputs reuse the input arrays (g2, g1, g0 may be
+  // in6[0], in6[1], in6[2]): each launch only overwrites arrays already read.
+  {
+    Pass p0;
+    p0.in(in6[1], true).in(in6[2], true).in(in6[5], true).out(g0, false);
+    p0.a.A[0][0] = spec(1.f, 0.f, 1, 1, -1, -1);
+    p0.a.A[0][1] = spec(1.f, 0.f, 2, 2, -1, -1);
+    p0.a.A[0][2] = spec(1.f, 0.f, 1, 2, -1, -1);
+    p0.a.B[0][0] = spec_const(1.f);
+    run_pass(g, 1, p0, 1, s);
+  }
+  {
+    Pass p1;
+    p1.in(in6[3], true).in(in6[4], true).out(g1, false);
+    p1.a.A[0][0] = spec(1.f, 0.f, 1, -1, -1, -1);
+    p1.a.A[0][1] = spec(1.f, 0.f, 2, -1, -1, -1);
+    p1.a.B[0][0] = spec_const(1.f);
+    run_pass(g, 1, p1, 1, s);
+  }
+  {
+    Pass p2;
+    p2.in(in6[0], true).out(g2, false);
+    p2.a.A[0][0] = spec_const(1.f);
+    p2.a.B[0][0] = spec_const(1.f);
+    run_pass(g, 1, p2, 1, s);
   }
 }
 
@@ -358,18 +417,7 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     ps.a.B[1][0] = spec(invn3, 0.f, X, NONE, TAB_INVK2, NONE);
     ps.a.B[2][0] = spec(invn3, 0.f, NONE, NONE, TAB_INVK2, NONE);
     run_pass(g, X, ps, 1, s);
-    Pass py;
-    py.in(sp[2], false).in(sp[3], false).in(sp[4], false);
-    for (int i = 0; i < 3; ++i) py.a.A[i][i] = spec_const(1.f);
-    // outputs in the order xx, yy, zz, xy, xz, yz
-    for (int o = 0; o < 6; ++o) py.out(sp[5 + o], true);
-    py.a.B[0][0] = spec_const(1.f);                      // xx
-    py.a.B[1][2] = spec(1.f, 0.f, Y, Y, NONE, NONE);     // yy
-    py.a.B[2][2] = spec(1.f, 0.f, Z, Z, NONE, NONE);     // zz
-    py.a.B[3][1] = spec(1.f, 0.f, Y, NONE, NONE, NONE);  // xy
-    py.a.B[4][1] = spec(1.f, 0.f, Z, NONE, NONE, NONE);  // xz
-    py.a.B[5][2] = spec(1.f, 0.f, Y, Z, NONE, NONE);     // yz
-    run_pass(g, Y, py, 3, s);
+    hessian_yi(g, sp[2], sp[3], sp[4], &sp[5], s);
     zi(g, &sp[5], g.phi, 6, s);
   }
   // 2LPT source and spherical-collapse divergence
@@ -398,15 +446,19 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     ps.a.B[0][0] = spec(0.f, 1.f, X, NONE, NONE, NONE);  // i k_x
     ps.a.B[1][0] = spec_const(1.f);
     run_pass(g, X, ps, 1, s);
-    Pass py;
-    py.in(sp[4], false).in(sp[5], false);
-    py.a.A[0][0] = spec_const(1.f);
-    py.a.A[1][1] = spec_const(1.f);
-    py.out(sp[6], true).out(sp[7], true).out(sp[8], true);
-    py.a.B[0][0] = spec_const(1.f);
-    py.a.B[1][1] = spec(0.f, 1.f, Y, NONE, NONE, NONE);
-    py.a.B[2][1] = spec(0.f, 1.f, Z, NONE, NONE, NONE);
-    run_pass(g, Y, py, 2, s);
+    {
+      Pass px;
+      px.in(sp[4], false).out(sp[6], true);
+      px.a.A[0][0] = spec_const(1.f);
+      px.a.B[0][0] = spec_const(1.f);
+      run_pass(g, Y, px, 1, s);
+      Pass pyz;
+      pyz.in(sp[5], false).out(sp[7], true).out(sp[8], true);
+      pyz.a.A[0][0] = spec_const(1.f);
+      pyz.a.B[0][0] = spec(0.f, 1.f, Y, NONE, NONE, NONE);
+      pyz.a.B[1][0] = spec(0.f, 1.f, Z, NONE, NONE, NONE);
+      run_pass(g, Y, pyz, 1, s);
+    }
     zi(g, &sp[6], g.psi, 3, s);
   }
   // CIC deposit (with plane-parallel RSD)
@@ -425,8 +477,10 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     ca.keyslot = g.keyslot;
     ca.sorted = g.sorted;
     ca.rho = g.rho;
+    ca.acc = g.acc;
     Timed tm(p, FZW_K_CIC, 4 * field_bytes(g));
-    launch_cic_deposit(ca, g.nc, s);
+    if (p->cic_method == FZW_CIC_ATOMIC) launch_cic_deposit_atomic(ca, g.nc, s);
+    else launch_cic_deposit(ca, g.nc, s);
   }
   // Web tensors (Section 2.8): T^w_ij = k_i k_j m_w(k) rho_k
   {
@@ -444,17 +498,7 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     }
     run_pass(g, X, ps, 1, s);
     for (int w = 0; w < p->W; ++w) {
-      Pass py;
-      py.in(sp[1 + 3 * w], false).in(sp[2 + 3 * w], false).in(sp[3 + 3 * w], false);
-      for (int i = 0; i < 3; ++i) py.a.A[i][i] = spec_const(1.f);
-      for (int o = 0; o < 6; ++o) py.out(sp[7 + o], true);
-      py.a.B[0][0] = spec_const(1.f);
-      py.a.B[1][2] = spec(1.f, 0.f, Y, Y, NONE, NONE);
-      py.a.B[2][2] = spec(1.f, 0.f, Z, Z, NONE, NONE);
-      py.a.B[3][1] = spec(1.f, 0.f, Y, NONE, NONE, NONE);
-      py.a.B[4][1] = spec(1.f, 0.f, Z, NONE, NONE, NONE);
-      py.a.B[5][2] = spec(1.f, 0.f, Y, Z, NONE, NONE);
-      run_pass(g, Y, py, 3, s);
+      hessian_yi(g, sp[1 + 3 * w], sp[2 + 3 * w], sp[3 + 3 * w], &sp[7], s);
       zi(g, &sp[7], &g.tens[6 * w], 6, s);
     }
   }
@@ -541,21 +585,7 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
     zf(g, g.tens, &sp[0], 6 * W, s);
     float* dd[1] = {g.drho_dir};
     zf(g, dd, &sp[12], 1, s);
-    for (int w = 0; w < W; ++w) {
-      Pass py;
-      for (int i = 0; i < 6; ++i) py.in(sp[6 * w + i], true);
-      py.a.A[0][0] = spec_const(1.f);                          // G2 = T_xx
-      py.a.A[1][3] = spec(1.f, 0.f, Y, NONE, NONE, NONE);      // G1 = k_y T_xy + k_z T_xz
-      py.a.A[1][4] = spec(1.f, 0.f, Z, NONE, NONE, NONE);
-      py.a.A[2][1] = spec(1.f, 0.f, Y, Y, NONE, NONE);         // G0 = k_y^2 T_yy + k_z^2 T_zz + k_y k_z T_yz
-      py.a.A[2][2] = spec(1.f, 0.f, Z, Z, NONE, NONE);
-      py.a.A[2][5] = spec(1.f, 0.f, Y, Z, NONE, NONE);
-      for (int o = 0; o < 3; ++o) {
-        py.out(sp[6 * w + o], false);
-        py.a.B[o][o] = spec_const(1.f);
-      }
-      run_pass(g, Y, py, 3, s);
-    }
+    for (int w = 0; w < W; ++w) hessian_yf(g, &sp[6 * w], sp[6 * w + 0], sp[6 * w + 1], sp[6 * w + 2], s);
     pure_pass(g, Y, false, &sp[12], 1, s);
     Pass ps;
     for (int w = 0; w < W; ++w) {
@@ -590,15 +620,15 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
   // ALPT adjoint: D = sum_j (-i k_j / k^2) rfft(dPsi_j)
   {
     zf(g, g.psi, &sp[0], 3, s);
-    Pass py;
-    py.in(sp[0], true).in(sp[1], true).in(sp[2], true);
-    py.a.A[0][0] = spec_const(1.f);
-    py.a.A[1][1] = spec(0.f, -1.f, Y, NONE, NONE, NONE);
-    py.a.A[1][2] = spec(0.f, -1.f, Z, NONE, NONE, NONE);
-    py.out(sp[0], false).out(sp[1], false);
-    py.a.B[0][0] = spec_const(1.f);
-    py.a.B[1][1] = spec_const(1.f);
-    run_pass(g, Y, py, 2, s);
+    pure_pass(g, Y, false, &sp[0], 1, s);
+    {
+      Pass pyz;
+      pyz.in(sp[1], true).in(sp[2], true).out(sp[1], false);
+      pyz.a.A[0][0] = spec(0.f, -1.f, Y, NONE, NONE, NONE);
+      pyz.a.A[0][1] = spec(0.f, -1.f, Z, NONE, NONE, NONE);
+      pyz.a.B[0][0] = spec_const(1.f);
+      run_pass(g, Y, pyz, 1, s);
+    }
     Pass ps;
     ps.in(sp[0], true).in(sp[1], true);
     ps.a.A[0][0] = spec(0.f, -1.f, X, NONE, TAB_INVK2, NONE);
@@ -630,19 +660,7 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
   // d nu_k = h / k^2 sum_ij k_i k_j rfft(d phi_ij) + direct ALPT term
   {
     zf(g, g.phi, &sp[5], 6, s);
-    Pass py;
-    for (int i = 0; i < 6; ++i) py.in(sp[5 + i], true);
-    py.a.A[0][0] = spec_const(1.f);
-    py.a.A[1][3] = spec(1.f, 0.f, Y, NONE, NONE, NONE);
-    py.a.A[1][4] = spec(1.f, 0.f, Z, NONE, NONE, NONE);
-    py.a.A[2][1] = spec(1.f, 0.f, Y, Y, NONE, NONE);
-    py.a.A[2][2] = spec(1.f, 0.f, Z, Z, NONE, NONE);
-    py.a.A[2][5] = spec(1.f, 0.f, Y, Z, NONE, NONE);
-    for (int o = 0; o < 3; ++o) {
-      py.out(sp[5 + o], false);
-      py.a.B[o][o] = spec_const(1.f);
-    }
-    run_pass(g, Y, py, 3, s);
+    hessian_yf(g, &sp[5], sp[5], sp[6], sp[7], s);
     Pass ps;
     ps.in(sp[5], true).in(sp[6], true).in(sp[7], true).in(sp[4], false);
     ps.a.A[0][0] = spec(invn3, 0.f, X, X, TAB_H, TAB_INVK2);
@@ -1032,6 +1050,21 @@ fzw_status fzw_fft_r2c(fzw_plan* p, int n, int batch, const float* in, void* out
 }
 fzw_status fzw_fft_c2r(fzw_plan* p, int n, int batch, const void* in_complex, float* out) {
   return fft_common(p, n, batch, in_complex, out, false);
+}
+
+fzw_status fzw_set_cic_method(fzw_plan* p, int method) {
+  if (!p || (method != FZW_CIC_SORTED && method != FZW_CIC_ATOMIC)) {
+    g_last_error = "fzw_set_cic_method: bad argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    for (auto& kv : p->graphs) {
+      (void)hipGraphExecDestroy(kv.second.e);
+      (void)hipGraphDestroy(kv.second.g);
+    }
+    p->graphs.clear();
+    p->cic_method = method;
+  });
 }
 
 fzw_status fzw_timing_enable(fzw_plan* p, int on) {

@@ -59,6 +59,8 @@ def load_library(path: str = _LIB_PATH):
     lib.fzw_get_field.argtypes = [vp, i, i, vp]
     lib.fzw_fft_r2c.argtypes = [vp, i, i, vp, vp]
     lib.fzw_fft_c2r.argtypes = [vp, i, i, vp, vp]
+    lib.fzw_set_cic_method.argtypes = [vp, i]
+    lib.fzw_set_cic_method.restype = ctypes.c_int
     lib.fzw_timing_enable.argtypes = [vp, i]
     lib.fzw_timing_enable.restype = ctypes.c_int
     lib.fzw_timing_read.argtypes = [vp, i, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(d)]
@@ -215,6 +217,11 @@ class Plan:
                                  _ptr(step, torch.float32), int(n_steps), _ptr(h_start, torch.float64),
                                  _ptr(h_end, torch.float64)), "fzw_leapfrog")
         return h_start, h_end
+
+    def set_cic_method(self, method: str):
+        """'sorted' (counting sort + gather, default) or 'atomic' (fixed-point
+        integer atomics); both give bit-identical densities."""
+        _check(_lib.fzw_set_cic_method(self._h, {"sorted": 0, "atomic": 1}[method]), "fzw_set_cic_method")
 
     def timing(self, on: bool):
         """Bracket every later launch with HIP events (per kernel class)."""
