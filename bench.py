@@ -8,7 +8,7 @@ synthetic white noise and synthetic counts.  One step = one forward + adjoint
 (value_and_grad) of that chain.  Also reported: the same step with 4 identical
 256^3 chains batched in one plan (grads/s counts every chain).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--copy-calibration]
 """
 import argparse
 import json
@@ -68,6 +68,19 @@ def cpu_baseline(w):
                       "scaled by %dx voxels to the 256^3 step" % (dt, scale)}
 
 
+def copy_calibration(torch, gib=1, reps=5):
+    """A plain device-to-device copy of known size: the reference that scales
+    the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    nbytes = gib << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes, "launches": reps}}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +89,8 @@ def main():
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU path "
@@ -84,6 +99,9 @@ def main():
 
     import numpy as np
     import torch
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     import fzw_inputs as fi
     from paper_2506_03969_amd import CosmoParams, Plan, WebParams
 

@@ -106,26 +106,63 @@ __device__ __forceinline__ void cic_locate(const CicArgs& a, long long p, int n,
   cz += cz < 0 ? n : 0;
 }
 
-// Key of every particle and its slot inside the bucket (integer atomics only).
-__global__ void cic_count_kernel(CicArgs a) {
+// Adds one to ctr[key] for every lane of the wave that passes `valid`, with
+// one atomic per distinct key in the wave (the particles of a wave sit on one
+// lattice line and land in a few columns).  The lanes are first grouped by key
+// with register-only lane reads; then the first lane of every group issues its
+// group's atomic, all groups in one instruction.  With RET, returns the lane's
+// slot: the counter's old value plus its rank among the lanes of equal key.
+// Every lane of the wave must call it (the grouping loop is wave-uniform).
+template <bool RET>
+__device__ __forceinline__ int wave_count(int* ctr, int key, bool valid) {
+  const int lane = (int)(threadIdx.x & 63);
+  int lead = lane, rank = 0, num = 0;
+  unsigned long long pm = __ballot(valid);
+  while (pm) {
+    const int leader = __ffsll((unsigned long long)pm) - 1;
+    const int lk = __builtin_amdgcn_readlane(key, leader);
+    const bool mine = ((pm >> lane) & 1ull) && key == lk;
+    const unsigned long long mm = __ballot(mine);
+    if (mine) {
+      lead = leader;
+      rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mm, 0u));
+    }
+    if (lane == leader) num = __popcll(mm);
+    pm &= ~mm;
+  }
+  int base = 0;
+  if (valid && lane == lead) {
+    if (RET) base = atomicAdd(ctr + key, num);
+    else atomicAdd(ctr + key, num);
+  }
+  if (RET) base = __shfl(base, lead);
+  return base + rank;
+}
+
+// Particles per destination column (x, y) of the mesh.
+__global__ __launch_bounds__(256) void cic_count_kernel(CicArgs a) {
   const long long nv = a.nv;
   const int n = a.n;
   const long long c = blockIdx.y;
   CicArgs b = a;
   for (int d = 0; d < 3; ++d) b.psi[d] = a.psi[d] + c * nv;
-  int* count = a.count + c * nv;
-  int2* ks = a.keyslot + c * nv;
-  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nv; p += (long long)gridDim.x * blockDim.x) {
-    int cx, cy, cz;
-    float tx, ty, tz;
-    cic_locate(b, p, n, cx, cy, cz, tx, ty, tz);
-    const int key = (cx * n + cy) * n + cz;
-    const int slot = atomicAdd(count + key, 1);
-    ks[p] = make_int2(key, slot);
+  int* count = a.count + c * (long long)n * n;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long p0 = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63u); p0 < nv; p0 += stride) {
+    const long long p = p0 + (threadIdx.x & 63);
+    const bool valid = p < nv;
+    int key = 0;
+    if (valid) {
+      int cx, cy, cz;
+      float tx, ty, tz;
+      cic_locate(b, p, n, cx, cy, cz, tx, ty, tz);
+      key = cx * n + cy;
+    }
+    wave_count<false>(count, key, valid);
   }
 }
 
-// Exclusive scan of the bucket counts: per-block totals, a single-block scan
+// Exclusive scan of the column counts: per-block totals, a single-block scan
 // of the totals, then per-block local scans.
 constexpr int kScanBlock = 4096;
 __global__ void scan_reduce_kernel(const int* __restrict__ count, long long nv, int* __restrict__ bsum, int nb) {
@@ -209,56 +246,88 @@ __global__ void scan_down_kernel(const int* __restrict__ count, long long nv, co
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) off[nv] = run;
 }
 
-// Scatter the fractional offsets into bucket order.
-__global__ void cic_scatter_kernel(CicArgs a) {
+// Scatter the fractional offsets into column order (any order inside a
+// column); the bucket z index travels in the .w lane.
+__global__ __launch_bounds__(256) void cic_scatter_kernel(CicArgs a) {
   const long long nv = a.nv;
   const int n = a.n;
   const long long c = blockIdx.y;
+  const long long ncol = (long long)n * n;
   CicArgs b = a;
   for (int d = 0; d < 3; ++d) b.psi[d] = a.psi[d] + c * nv;
-  const int2* ks = a.keyslot + c * nv;
-  const int* off = a.offset + c * (nv + 1);
+  int* cursor = a.count + c * ncol;
+  const int* off = a.offset + c * (ncol + 1);
   float4* sorted = a.sorted + c * nv;
-  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nv; p += (long long)gridDim.x * blockDim.x) {
-    int cx, cy, cz;
-    float tx, ty, tz;
-    cic_locate(b, p, n, cx, cy, cz, tx, ty, tz);
-    const int2 k = ks[p];
-    sorted[off[k.x] + k.y] = make_float4(tx, ty, tz, 0.f);
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long p0 = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63u); p0 < nv; p0 += stride) {
+    const long long p = p0 + (threadIdx.x & 63);
+    const bool valid = p < nv;
+    int cx = 0, cy = 0, cz = 0;
+    float tx = 0.f, ty = 0.f, tz = 0.f;
+    if (valid) cic_locate(b, p, n, cx, cy, cz, tx, ty, tz);
+    const int key = cx * n + cy;
+    const int slot = wave_count<true>(cursor, key, valid);
+    if (valid) {
+      const int dst = off[key] + slot;
+      if (dst < off[key + 1]) sorted[dst] = make_float4(tx, ty, tz, __int_as_float(cz));
+    }
   }
 }
 
-// Gather deposit: every node sums the trilinear weights of the particles in
-// the 8 buckets that touch it.  The sum is accumulated in 64-bit fixed point
-// (2^-32 resolution), so it does not depend on the order of particles inside
-// a bucket: the result is bitwise reproducible.
-__global__ void cic_gather_kernel(CicArgs a) {
+// Gather deposit, tiled: a workgroup owns kLineTile x kLineTile lines of nodes
+// along z.  It streams the particles of the (kLineTile+1)^2 source columns
+// that touch those lines (contiguous in bucket order, so the loads coalesce)
+// and adds each trilinear weight, in 64-bit fixed point (2^-32 resolution),
+// to an LDS copy of its lines with integer atomics.  Integer sums do not
+// depend on order, so the density is bitwise reproducible and equal to that of
+// the global-atomic deposit below.
+constexpr int kLineTile = 4;
+__global__ __launch_bounds__(256) void cic_gather_tiles_kernel(CicArgs a) {
+  extern __shared__ unsigned long long acc_lds[];
+  constexpr int T = kLineTile;
   const long long nv = a.nv;
   const int n = a.n;
   const long long c = blockIdx.y;
-  const int* off = a.offset + c * (nv + 1);
+  const int* off = a.offset + c * ((long long)n * n + 1);
   const float4* sorted = a.sorted + c * nv;
   float* rho = a.rho + c * nv;
-  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nv; q += (long long)gridDim.x * blockDim.x) {
-    const int x = (int)(q / ((long long)n * n));
-    const int y = (int)((q / n) % n);
-    const int z = (int)(q % n);
-    long long acc = 0;
+  const int tiles = n / T;
+  const int x0 = (blockIdx.x / tiles) * T, y0 = (blockIdx.x % tiles) * T;
+  const int t = threadIdx.x;
+  for (int i = t; i < T * T * n; i += blockDim.x) acc_lds[i] = 0ull;
+  __syncthreads();
+  for (int col = 0; col < (T + 1) * (T + 1); ++col) {
+    const int rx = col / (T + 1), ry = col % (T + 1);
+    int bx = x0 - 1 + rx, by = y0 - 1 + ry;
+    bx += bx < 0 ? n : 0;
+    by += by < 0 ? n : 0;
+    const int lo = off[bx * n + by], hi = off[bx * n + by + 1];
+    for (int s = lo + t; s < hi; s += blockDim.x) {
+      const float4 q = sorted[s];
+      const int bz = __float_as_int(q.w);
+      if ((unsigned)bz >= (unsigned)n) continue;   // never taken: every slot holds a particle
+      const int bz1 = bz + 1 == n ? 0 : bz + 1;
 #pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
-      const int bx = ox ? (x == 0 ? n - 1 : x - 1) : x;
-      const int by = oy ? (y == 0 ? n - 1 : y - 1) : y;
-      const int bz = oz ? (z == 0 ? n - 1 : z - 1) : z;
-      const int key = (bx * n + by) * n + bz;
-      const int lo = off[key], hi = off[key + 1];
-      for (int s = lo; s < hi; ++s) {
-        const float4 t = sorted[s];
-        const float w = (ox ? t.x : 1.f - t.x) * (oy ? t.y : 1.f - t.y) * (oz ? t.z : 1.f - t.z);
-        acc += __float2ll_rn(w * 4294967296.0f);
+      for (int ox = 0; ox < 2; ++ox) {
+        const int lx = rx - 1 + ox;
+        if (lx < 0 || lx >= T) continue;
+#pragma unroll
+        for (int oy = 0; oy < 2; ++oy) {
+          const int ly = ry - 1 + oy;
+          if (ly < 0 || ly >= T) continue;
+          const float wxy = (ox ? q.x : 1.f - q.x) * (oy ? q.y : 1.f - q.y);
+          unsigned long long* line = acc_lds + (lx * T + ly) * n;
+          atomicAdd(line + bz, (unsigned long long)__float2ll_rn(wxy * (1.f - q.z) * 4294967296.0f));
+          atomicAdd(line + bz1, (unsigned long long)__float2ll_rn(wxy * q.z * 4294967296.0f));
+        }
       }
     }
-    rho[q] = (float)((double)acc * (1.0 / 4294967296.0));
+  }
+  __syncthreads();
+  for (int i = t; i < T * T * n; i += blockDim.x) {
+    const int l = i / n, z = i % n;
+    const int x = x0 + l / T, y = y0 + l % T;
+    rho[((long long)x * n + y) * n + z] = (float)((double)(long long)acc_lds[i] * (1.0 / 4294967296.0));
   }
 }
 
@@ -341,15 +410,22 @@ void launch_cic_deposit_atomic(const CicArgs& a, int chains, hipStream_t s) {
 
 void launch_cic_deposit(const CicArgs& a, int chains, hipStream_t s) {
   const long long nv = a.nv;
-  launch_fill_i32(a.count, nv * chains, 0, s);
+  const long long ncol = (long long)a.n * a.n;
+  launch_fill_i32(a.count, ncol * chains, 0, s);
   dim3 gp(grid_for(nv, 256, 32768), chains);
   hipLaunchKernelGGL(cic_count_kernel, gp, dim3(256), 0, s, a);
-  const int nb = (int)((nv + kScanBlock - 1) / kScanBlock);
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb, chains), dim3(256), 0, s, a.count, nv, a.bsum, nb);
+  const int nb = (int)((ncol + kScanBlock - 1) / kScanBlock);
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb, chains), dim3(256), 0, s, a.count, ncol, a.bsum, nb);
   hipLaunchKernelGGL(scan_blocks_kernel, dim3(chains), dim3(1024), 0, s, a.bsum, nb);
-  hipLaunchKernelGGL(scan_down_kernel, dim3(nb, chains), dim3(256), 0, s, a.count, nv, a.bsum, nb, a.offset);
+  hipLaunchKernelGGL(scan_down_kernel, dim3(nb, chains), dim3(256), 0, s, a.count, ncol, a.bsum, nb, a.offset);
+  launch_fill_i32(a.count, ncol * chains, 0, s);
   hipLaunchKernelGGL(cic_scatter_kernel, gp, dim3(256), 0, s, a);
-  hipLaunchKernelGGL(cic_gather_kernel, gp, dim3(256), 0, s, a);
+  const int tiles = a.n / kLineTile;
+  const size_t lds = sizeof(unsigned long long) * kLineTile * kLineTile * a.n;
+  if (lds > 32768)
+    (void)hipFuncSetAttribute((const void*)cic_gather_tiles_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+  hipLaunchKernelGGL(cic_gather_tiles_kernel, dim3(tiles * tiles, chains), dim3(256), lds, s, a);
 }
 
 void launch_cic_adjoint(const CicArgs& a, int chains, hipStream_t s) {
@@ -639,8 +715,10 @@ __global__ __launch_bounds__(256) void voxel_bwd_kernel(VoxelArgs a) {
   constexpr int R = W == 1 ? 4 : 16;
   constexpr int NE = R * 4;
   constexpr int G = 256 / NE;          // voxel groups per entry
-  __shared__ float sp[R][256];
-  __shared__ double sd[4][256];
+  // rows padded to an odd stride: the reduce reads 16 (resp. 4) rows at one
+  // column per instruction, which would otherwise fall in one LDS bank
+  __shared__ float sp[R][257];
+  __shared__ double sd[4][257];
   __shared__ double sacc[256];
   const long long c = blockIdx.y;
   const long long nv = a.nv;
@@ -670,7 +748,18 @@ __global__ __launch_bounds__(256) void voxel_bwd_kernel(VoxelArgs a) {
       const double l1p = log1p(nb / beta);
       double dg = 0.0;
       if (n <= 64) {
-        for (int m = 0; m < n; ++m) dg += 1.0 / (beta + (double)m);
+        // sum of 1/(beta+m) over m < n, as fractions of up to 8 terms (one
+        // division each; the denominator (beta+64)^8 stays inside float64)
+        for (int m0 = 0; m0 < n; m0 += 8) {
+          double pq = 0.0, qq = 1.0;
+          const int m1 = min(n, m0 + 8);
+          for (int m = m0; m < m1; ++m) {
+            const double bm = beta + (double)m;
+            pq = fma(pq, bm, qq);
+            qq *= bm;
+          }
+          dg += pq / qq;
+        }
       } else {
         dg = nb_digamma_big(n, beta);
       }
@@ -745,7 +834,7 @@ __global__ __launch_bounds__(256) void voxel_bwd_kernel(VoxelArgs a) {
 }
 
 // Sum of per-block partials in a fixed order (one workgroup per chain).
-// mode 0: sum f -> ln C; mode 1: (logL, G); mode 2: bias-table gradient.
+// mode 0: sum f -> ln C; mode 1: (logL, G).
 __global__ void finalize_kernel(FinalArgs a) {
   __shared__ double red[4];
   const long long c = blockIdx.x;
@@ -772,16 +861,20 @@ __global__ void finalize_kernel(FinalArgs a) {
       sc[kScalG] = s2;
       if (a.logl) a.logl[c] = logl;
     }
-  } else {
-    // one block-wide fixed-order sum per table entry
-    const int ne = a.ne;
-    for (int e = 0; e < ne; ++e) {
-      double s = 0.0;
-      for (int i = threadIdx.x; i < a.nblk; i += blockDim.x) s += a.partial[(c * a.nblk + i) * ne + e];
-      s = block_sum(s, red);
-      if (threadIdx.x == 0) a.dtable[c * ne + e] = (float)s;
-    }
   }
+}
+
+// Bias-table gradient: one workgroup per (entry, chain), fixed-order sum of
+// the per-block partials.
+__global__ void finalize_table_kernel(FinalArgs a) {
+  __shared__ double red[4];
+  const int e = blockIdx.x;
+  const long long c = blockIdx.y;
+  const int ne = a.ne;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < a.nblk; i += blockDim.x) s += a.partial[(c * a.nblk + i) * ne + e];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) a.dtable[c * ne + e] = (float)s;
 }
 
 void launch_voxel_fwd(int w, const VoxelArgs& a, int chains, int nblk, hipStream_t s) {
@@ -798,7 +891,8 @@ void launch_likelihood(const LikeArgs& a, int chains, int nblk, hipStream_t s) {
   hipLaunchKernelGGL(likelihood_kernel, dim3(nblk, chains), dim3(256), 0, s, a);
 }
 void launch_finalize(const FinalArgs& a, int chains, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(chains), dim3(256), 0, s, a);
+  if (a.mode == 2) hipLaunchKernelGGL(finalize_table_kernel, dim3(a.ne, chains), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(finalize_kernel, dim3(chains), dim3(256), 0, s, a);
 }
 
 // ------------------------------------------------------ data-only constants

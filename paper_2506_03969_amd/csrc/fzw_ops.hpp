@@ -22,11 +22,10 @@ struct CicArgs {
   float scale[3];        // displacement -> cell units per axis (RSD factor included)
   int n;
   long long nv;
-  int* count;            // [chains][nv]
-  int* offset;           // [chains][nv+1]
-  int* bsum;             // [chains][nv/4096 rounded up]
-  int2* keyslot;         // [chains][nv]
-  float4* sorted;        // [chains][nv]
+  int* count;            // [chains][n*n] particles per column, then the scatter cursor
+  int* offset;           // [chains][n*n+1] column starts in the sorted array
+  int* bsum;             // [chains][n*n/4096 rounded up]
+  float4* sorted;        // [chains][nv] (tx, ty, tz, bucket z as int bits) in column order
   unsigned long long* acc;  // [chains][nv] fixed-point accumulator (atomic deposit), kept zero
   float* rho;            // [chains][nv]
   const float* drho;     // adjoint input

@@ -98,7 +98,6 @@ struct Group {
   int* count = nullptr;
   int* offset = nullptr;
   int* bsum = nullptr;
-  int2* keyslot = nullptr;
   float4* sorted = nullptr;
   unsigned long long* acc = nullptr;
 };
@@ -265,10 +264,10 @@ void alloc_group(fzw_plan* p, Group& g) {
   g.drho_dir = dalloc<float>(p, nf);
   g.drho = dalloc<float>(p, nf);
   for (auto& s : g.spec) s = dalloc<float2>(p, nsp);
-  g.count = dalloc<int>(p, nf);
-  g.offset = dalloc<int>(p, (size_t)g.nc * (g.nv + 1));
-  g.bsum = dalloc<int>(p, (size_t)g.nc * ((g.nv + 4095) / 4096));
-  g.keyslot = dalloc<int2>(p, nf);
+  const size_t ncol = (size_t)g.n * g.n;
+  g.count = dalloc<int>(p, (size_t)g.nc * ncol);
+  g.offset = dalloc<int>(p, (size_t)g.nc * (ncol + 1));
+  g.bsum = dalloc<int>(p, (size_t)g.nc * ((ncol + 4095) / 4096));
   g.sorted = dalloc<float4>(p, nf);
   g.acc = dalloc<unsigned long long>(p, nf);
   HIPCHK(hipMemset(g.acc, 0, nf * sizeof(unsigned long long)));
@@ -474,7 +473,6 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     ca.count = g.count;
     ca.offset = g.offset;
     ca.bsum = g.bsum;
-    ca.keyslot = g.keyslot;
     ca.sorted = g.sorted;
     ca.rho = g.rho;
     ca.acc = g.acc;
