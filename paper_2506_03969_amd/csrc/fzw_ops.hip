@@ -86,24 +86,39 @@ void launch_lpt_bwd(const LptArgs& a, hipStream_t s) {
 // ---------------------------------------------------------------------- CIC
 // Cell of a particle: lattice node + floor(Psi * scale); the fractional part
 // is formed from the displacement alone, never from absolute coordinates.
-__device__ __forceinline__ void cic_locate(const CicArgs& a, long long p, int n, int& cx, int& cy, int& cz,
+__device__ __forceinline__ int wrap_index(int c, int n) {
+  if (c >= 0 && c < n) return c;
+  if (c >= n && c < 2 * n) return c - n;
+  if (c < 0 && c >= -n) return c + n;
+  const int r = c % n;   // displacements of more than a box length
+  return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ void cic_locate(const CicArgs& a, int p, int n, int& cx, int& cy, int& cz,
                                            float& tx, float& ty, float& tz) {
-  const int ix = (int)(p / ((long long)n * n));
-  const int iy = (int)((p / n) % n);
-  const int iz = (int)(p % n);
-  const float dx = a.psi[0][p] * a.scale[0];
-  const float dy = a.psi[1][p] * a.scale[1];
-  const float dz = a.psi[2][p] * a.scale[2];
-  const float fx = floorf(dx), fy = floorf(dy), fz = floorf(dz);
-  tx = dx - fx;
-  ty = dy - fy;
-  tz = dz - fz;
-  cx = (ix + (int)fx) % n;
-  cy = (iy + (int)fy) % n;
-  cz = (iz + (int)fz) % n;
-  cx += cx < 0 ? n : 0;
-  cy += cy < 0 ? n : 0;
-  cz += cz < 0 ? n : 0;
+  const int q = (int)fast_div((unsigned)p, a.dn);
+  const int iz = p - q * n;
+  const int ix = (int)fast_div((unsigned)q, a.dn);
+  const int iy = q - ix * n;
+  {
+    // no fma contraction here: fusing psi * scale - floor into one fma is a
+    // per-kernel choice of the compiler, and every deposit and its adjoint
+    // must see the same fractional offsets bit for bit
+#pragma clang fp contract(off)
+    const float dx = a.psi[0][p] * a.scale[0];
+    const float dy = a.psi[1][p] * a.scale[1];
+    const float dz = a.psi[2][p] * a.scale[2];
+    const float fx = floorf(dx), fy = floorf(dy), fz = floorf(dz);
+    tx = dx - fx;
+    ty = dy - fy;
+    tz = dz - fz;
+    cx = ix + (int)fx;
+    cy = iy + (int)fy;
+    cz = iz + (int)fz;
+  }
+  cx = wrap_index(cx, n);
+  cy = wrap_index(cy, n);
+  cz = wrap_index(cz, n);
 }
 
 // Adds one to ctr[key] for every lane of the wave that passes `valid`, with
@@ -155,7 +170,7 @@ __global__ __launch_bounds__(256) void cic_count_kernel(CicArgs a) {
     if (valid) {
       int cx, cy, cz;
       float tx, ty, tz;
-      cic_locate(b, p, n, cx, cy, cz, tx, ty, tz);
+      cic_locate(b, (int)p, n, cx, cy, cz, tx, ty, tz);
       key = cx * n + cy;
     }
     wave_count<false>(count, key, valid);
@@ -247,7 +262,7 @@ __global__ void scan_down_kernel(const int* __restrict__ count, long long nv, co
 }
 
 // Scatter the fractional offsets into column order (any order inside a
-// column); the bucket z index travels in the .w lane.
+// column); the bucket's y and z indices travel in the .w lane as by << 16 | bz.
 __global__ __launch_bounds__(256) void cic_scatter_kernel(CicArgs a) {
   const long long nv = a.nv;
   const int n = a.n;
@@ -264,19 +279,19 @@ __global__ __launch_bounds__(256) void cic_scatter_kernel(CicArgs a) {
     const bool valid = p < nv;
     int cx = 0, cy = 0, cz = 0;
     float tx = 0.f, ty = 0.f, tz = 0.f;
-    if (valid) cic_locate(b, p, n, cx, cy, cz, tx, ty, tz);
+    if (valid) cic_locate(b, (int)p, n, cx, cy, cz, tx, ty, tz);
     const int key = cx * n + cy;
     const int slot = wave_count<true>(cursor, key, valid);
     if (valid) {
       const int dst = off[key] + slot;
-      if (dst < off[key + 1]) sorted[dst] = make_float4(tx, ty, tz, __int_as_float(cz));
+      if (dst < off[key + 1]) sorted[dst] = make_float4(tx, ty, tz, __int_as_float((cy << 16) | cz));
     }
   }
 }
 
 // Gather deposit, tiled: a workgroup owns kLineTile x kLineTile lines of nodes
 // along z.  It streams the particles of the (kLineTile+1)^2 source columns
-// that touch those lines (contiguous in bucket order, so the loads coalesce)
+// that touch those lines (contiguous in column order, so the loads coalesce)
 // and adds each trilinear weight, in 64-bit fixed point (2^-32 resolution),
 // to an LDS copy of its lines with integer atomics.  Integer sums do not
 // depend on order, so the density is bitwise reproducible and equal to that of
@@ -296,16 +311,32 @@ __global__ __launch_bounds__(256) void cic_gather_tiles_kernel(CicArgs a) {
   const int t = threadIdx.x;
   for (int i = t; i < T * T * n; i += blockDim.x) acc_lds[i] = 0ull;
   __syncthreads();
-  for (int col = 0; col < (T + 1) * (T + 1); ++col) {
-    const int rx = col / (T + 1), ry = col % (T + 1);
-    int bx = x0 - 1 + rx, by = y0 - 1 + ry;
+  // the source columns (bx, y0-1 .. y0+T-1) of one bx are consecutive in
+  // column order: one range per bx, two where y0-1 wraps to n-1
+  for (int seg = 0; seg < 2 * (T + 1); ++seg) {
+    const int rx = seg >> 1;
+    int bx = x0 - 1 + rx;
     bx += bx < 0 ? n : 0;
-    by += by < 0 ? n : 0;
-    const int lo = off[bx * n + by], hi = off[bx * n + by + 1];
+    const int* ob = off + bx * n;
+    int lo, hi;
+    if (y0 > 0) {
+      if (seg & 1) continue;
+      lo = ob[y0 - 1];
+      hi = ob[y0 + T];
+    } else if (seg & 1) {
+      lo = ob[n - 1];
+      hi = ob[n];
+    } else {
+      lo = ob[0];
+      hi = ob[T];
+    }
     for (int s = lo + t; s < hi; s += blockDim.x) {
       const float4 q = sorted[s];
-      const int bz = __float_as_int(q.w);
-      if ((unsigned)bz >= (unsigned)n) continue;   // never taken: every slot holds a particle
+      const int yz = __float_as_int(q.w);
+      const int bz = yz & 0xffff;
+      int ry = (yz >> 16) - y0 + 1;
+      ry -= ry > T ? n : 0;
+      if ((unsigned)bz >= (unsigned)n || (unsigned)ry > (unsigned)T) continue;   // never taken
       const int bz1 = bz + 1 == n ? 0 : bz + 1;
 #pragma unroll
       for (int ox = 0; ox < 2; ++ox) {
@@ -343,7 +374,7 @@ __global__ void cic_adjoint_kernel(CicArgs a) {
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nv; p += (long long)gridDim.x * blockDim.x) {
     int cx, cy, cz;
     float tx, ty, tz;
-    cic_locate(b, p, n, cx, cy, cz, tx, ty, tz);
+    cic_locate(b, (int)p, n, cx, cy, cz, tx, ty, tz);
     const int nx = cx + 1 == n ? 0 : cx + 1;
     const int ny = cy + 1 == n ? 0 : cy + 1;
     const int nz = cz + 1 == n ? 0 : cz + 1;
@@ -378,7 +409,7 @@ __global__ void cic_atomic_kernel(CicArgs a) {
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nv; p += (long long)gridDim.x * blockDim.x) {
     int cx, cy, cz;
     float tx, ty, tz;
-    cic_locate(b, p, n, cx, cy, cz, tx, ty, tz);
+    cic_locate(b, (int)p, n, cx, cy, cz, tx, ty, tz);
     const int nx = cx + 1 == n ? 0 : cx + 1;
     const int ny = cy + 1 == n ? 0 : cy + 1;
     const int nz = cz + 1 == n ? 0 : cz + 1;
@@ -401,14 +432,18 @@ __global__ void cic_convert_kernel(CicArgs a, long long total) {
   }
 }
 
-void launch_cic_deposit_atomic(const CicArgs& a, int chains, hipStream_t s) {
+void launch_cic_deposit_atomic(const CicArgs& a0, int chains, hipStream_t s) {
+  CicArgs a = a0;
+  a.dn = make_fastdiv((unsigned)a.n);
   dim3 gp(grid_for(a.nv, 256, 32768), chains);
   hipLaunchKernelGGL(cic_atomic_kernel, gp, dim3(256), 0, s, a);
   const long long total = a.nv * chains;
   hipLaunchKernelGGL(cic_convert_kernel, dim3(grid_for(total, 256, 32768)), dim3(256), 0, s, a, total);
 }
 
-void launch_cic_deposit(const CicArgs& a, int chains, hipStream_t s) {
+void launch_cic_deposit(const CicArgs& a0, int chains, hipStream_t s) {
+  CicArgs a = a0;
+  a.dn = make_fastdiv((unsigned)a.n);
   const long long nv = a.nv;
   const long long ncol = (long long)a.n * a.n;
   launch_fill_i32(a.count, ncol * chains, 0, s);
@@ -428,7 +463,9 @@ void launch_cic_deposit(const CicArgs& a, int chains, hipStream_t s) {
   hipLaunchKernelGGL(cic_gather_tiles_kernel, dim3(tiles * tiles, chains), dim3(256), lds, s, a);
 }
 
-void launch_cic_adjoint(const CicArgs& a, int chains, hipStream_t s) {
+void launch_cic_adjoint(const CicArgs& a0, int chains, hipStream_t s) {
+  CicArgs a = a0;
+  a.dn = make_fastdiv((unsigned)a.n);
   dim3 gp(grid_for(a.nv, 256, 32768), chains);
   hipLaunchKernelGGL(cic_adjoint_kernel, gp, dim3(256), 0, s, a);
 }
@@ -436,25 +473,56 @@ void launch_cic_adjoint(const CicArgs& a, int chains, hipStream_t s) {
 // ------------------------------------------------------- symmetric 3x3 eigen
 // Eigenvalues of a symmetric 3x3 tensor, descending, by the trigonometric
 // solution of the characteristic cubic (Smith 1961).
-__device__ __forceinline__ void eig3_values(const float t[6], float lam[3], float& q, float& p) {
+// Eigenvalues of a symmetric 3x3 tensor from its normalised characteristic
+// cubic: with q = tr T / 3, p^2 = tr((T - qI)^2) / 6 and B = (T - qI) / p, the
+// eigenvalues are q + p beta where beta^3 - 3 beta = det B = 2r, |r| <= 1.
+// The root farthest from the other two is the largest one when r >= 0 and the
+// smallest otherwise, and its magnitude lies in [sqrt 3, 2], where the cubic's
+// slope is at least 6: two Newton steps from the chord through the end points
+// reach float precision, with no trigonometric functions.  Returns that root
+// (beta_iso) and whether it is the largest (top); p = 0 flags T = qI.
+__device__ __forceinline__ void eig3_cubic(const float t[6], float& q, float& p, float& beta_iso, bool& top) {
   q = (t[0] + t[1] + t[2]) * (1.f / 3.f);
   const float a = t[0] - q, b = t[1] - q, c = t[2] - q;
   const float p2 = (a * a + b * b + c * c + 2.f * (t[3] * t[3] + t[4] * t[4] + t[5] * t[5])) * (1.f / 6.f);
+  beta_iso = 0.f;
+  top = true;
   if (!(p2 > 0.f)) {
-    lam[0] = lam[1] = lam[2] = q;
     p = 0.f;
     return;
   }
   p = sqrtf(p2);
-  const float ip = 1.f / p;
+  // hardware reciprocals (about 1 ulp): a uniform scale error of B moves r by
+  // a few ulp, and the Newton corrections are self-correcting
+  const float ip = __builtin_amdgcn_rcpf(p);
   const float ba = a * ip, bb = b * ip, bc = c * ip, bxy = t[3] * ip, bxz = t[4] * ip, byz = t[5] * ip;
   const float det = ba * (bb * bc - byz * byz) - bxy * (bxy * bc - byz * bxz) + bxz * (bxy * byz - bb * bxz);
-  float r = 0.5f * det;
-  r = fminf(1.f, fmaxf(-1.f, r));
-  const float phi = acosf(r) * (1.f / 3.f);
-  lam[0] = q + 2.f * p * cosf(phi);
-  lam[2] = q + 2.f * p * cosf(phi + 2.0943951023931954923f);
-  lam[1] = 3.f * q - lam[0] - lam[2];
+  const float r = fminf(1.f, fmaxf(-1.f, 0.5f * det));
+  top = r >= 0.f;
+  const float ra = fabsf(r);
+  float x = 1.7320508075688772f + 0.2679491924311228f * ra;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const float x2 = x * x;
+    x -= (x * (x2 - 3.f) - 2.f * ra) * __builtin_amdgcn_rcpf(3.f * (x2 - 1.f));
+  }
+  beta_iso = top ? x : -x;
+}
+
+// All three eigenvalues (descending) from the isolated root: the other two
+// solve beta^2 + beta_iso beta + beta_iso^2 - 3 = 0.
+__device__ __forceinline__ void eig3_all(float q, float p, float beta_iso, bool top, float lam[3]) {
+  const float s = sqrtf(fmaxf(0.f, 12.f - 3.f * beta_iso * beta_iso));
+  const float hi = 0.5f * (-beta_iso + s), lo = 0.5f * (-beta_iso - s);
+  if (top) {
+    lam[0] = q + p * beta_iso;
+    lam[1] = q + p * hi;
+    lam[2] = q + p * lo;
+  } else {
+    lam[0] = q + p * hi;
+    lam[1] = q + p * lo;
+    lam[2] = q + p * beta_iso;
+  }
 }
 
 __device__ __forceinline__ void cross3(const float* a, const float* b, float* c) {
@@ -511,23 +579,27 @@ __device__ __forceinline__ void sym_mul(const float t[6], const float* x, float*
 __device__ __forceinline__ float dot3(const float* a, const float* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
 // Eigen-decomposition of a symmetric 3x3 tensor that stays accurate for
-// nearly equal eigenvalues: the trigonometric solution only picks the
+// nearly equal eigenvalues: the characteristic cubic only supplies the
 // eigenvalue farthest from the other two; its eigenvector (a cross product of
 // two rows of T - l I, well conditioned because that eigenvalue is isolated)
 // is taken first, and the remaining pair is the exact Jacobi rotation of T
 // restricted to the orthogonal plane.  Returns eigenvalues descending and the
 // unit eigenvectors v1 (largest) and v3 (smallest).
 __device__ __forceinline__ void eig3_robust(const float t[6], float lam[3], float v1[3], float v3[3]) {
-  float q, p;
-  float l0[3];
-  eig3_values(t, l0, q, p);
+  float q, p, beta;
+  bool top;
+  eig3_cubic(t, q, p, beta, top);
   v1[0] = 1.f; v1[1] = 0.f; v1[2] = 0.f;
   v3[0] = 0.f; v3[1] = 0.f; v3[2] = 1.f;
-  lam[0] = l0[0]; lam[1] = l0[1]; lam[2] = l0[2];
-  if (!(p > 0.f)) return;
-  const bool top = (l0[0] - l0[1]) >= (l0[1] - l0[2]);
+  if (!(p > 0.f)) {
+    lam[0] = lam[1] = lam[2] = q;
+    return;
+  }
   float v[3];
-  if (!eig3_vector(t, top ? l0[0] : l0[2], (p * p) * (p * p) * 81.f, v)) return;
+  if (!eig3_vector(t, q + p * beta, (p * p) * (p * p) * 81.f, v)) {
+    eig3_all(q, p, beta, top, lam);
+    return;
+  }
   float u[3], w[3], tu[3], tw[3], tv[3];
   any_orthogonal(v, u);
   cross3(v, u, w);

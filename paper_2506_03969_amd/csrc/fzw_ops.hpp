@@ -17,15 +17,36 @@ struct LptArgs {
   long long n;
 };
 
+// Division by a fixed divisor d > 0 of dividends below 2^31, as a multiply
+// and a shift: s = ceil(log2 d), m = floor(2^(32+s) / d) + 1.  The rounding
+// error of m stays below 1/(2d) of a unit, so the quotient is exact.
+struct FastDiv {
+  unsigned d = 1, s = 0;
+  unsigned long long m = 0x100000001ull;
+};
+inline FastDiv make_fastdiv(unsigned d) {
+  FastDiv f;
+  f.d = d;
+  unsigned s = 0;
+  while ((1ull << s) < d) ++s;
+  f.s = s;
+  f.m = (unsigned long long)((((unsigned __int128)1) << (32 + s)) / d) + 1ull;
+  return f;
+}
+__device__ __forceinline__ unsigned fast_div(unsigned x, const FastDiv& f) {
+  return (unsigned)(((unsigned long long)x * f.m) >> (32 + f.s));
+}
+
 struct CicArgs {
   const float* psi[3];
   float scale[3];        // displacement -> cell units per axis (RSD factor included)
   int n;
+  FastDiv dn;            // division by n (set by the launchers)
   long long nv;
   int* count;            // [chains][n*n] particles per column, then the scatter cursor
   int* offset;           // [chains][n*n+1] column starts in the sorted array
   int* bsum;             // [chains][n*n/4096 rounded up]
-  float4* sorted;        // [chains][nv] (tx, ty, tz, bucket z as int bits) in column order
+  float4* sorted;        // [chains][nv] (tx, ty, tz, bits of (by << 16 | bz)) in column order
   unsigned long long* acc;  // [chains][nv] fixed-point accumulator (atomic deposit), kept zero
   float* rho;            // [chains][nv]
   const float* drho;     // adjoint input
