@@ -698,6 +698,8 @@ struct VoxelCore {
       for (int c = 0; c < 6; ++c) t6[w][c] = a.tens[w * 6 + c][i];
       eig3_robust(t6[w], lam[w], v1[w], v3[w]);
       web_memberships(lam[w], a.steep, a.lam_th, wgt[w], pm[w]);
+      // one web at a time: interleaving the two solves doubles the live registers
+      __builtin_amdgcn_sched_barrier(0);
     }
     if (W == 1) {
 #pragma unroll
@@ -708,12 +710,16 @@ struct VoxelCore {
 #pragma unroll
         for (int k = 0; k < 4; ++k) preg[4 * j + k] = pm[0][j] * pm[W - 1][k];
     }
+    theta[0] = theta[1] = theta[2] = theta[3] = 0.f;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      float s = 0.f;
-#pragma unroll
-      for (int r = 0; r < R; ++r) s += preg[r] * tab[r * 4 + c];
-      theta[c] = s;
+    for (int r = 0; r < R; ++r) {
+      const float4 tr = reinterpret_cast<const float4*>(tab)[r];
+      theta[0] += preg[r] * tr.x;
+      theta[1] += preg[r] * tr.y;
+      theta[2] += preg[r] * tr.z;
+      theta[3] += preg[r] * tr.w;
+      // four table rows at a time: hoisting every read keeps all 4R entries live
+      if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
     x = fmaxf(rho, a.x_floor);
     lnx = ::logf(x);
@@ -725,10 +731,15 @@ struct VoxelCore {
 
 template <int W>
 __global__ __launch_bounds__(256) void voxel_fwd_kernel(VoxelArgs a) {
+  constexpr int NE = W == 1 ? 16 : 64;
   __shared__ double red[4];
+  // the bias table sits in LDS: read from global memory inside the loop it is
+  // held in vector registers (the compiler cannot prove it unwritten)
+  __shared__ __align__(16) float tab[NE];
   const long long c = blockIdx.y;
   const long long nv = a.nv;
-  const float* tab = a.table + c * (W == 1 ? 16 : 64);
+  if (threadIdx.x < NE) tab[threadIdx.x] = a.table[c * NE + threadIdx.x];
+  __syncthreads();
   VoxelArgs b = a;
   for (int k = 0; k < 6 * W; ++k) b.tens[k] = a.tens[k] + c * nv;
   double sf = 0.0;
@@ -744,12 +755,17 @@ __global__ __launch_bounds__(256) void voxel_fwd_kernel(VoxelArgs a) {
 }
 
 // Likelihood pass: needs ln C = ln N_tr - ln sum f from the reduced partials.
-// Per-voxel terms in FP32 (accurate library functions), sums in FP64.
+// Per-voxel terms in FP32 (accurate library functions), sums in FP64.  With
+// ghat set it also forms, in float64 where the terms cancel, what the backward
+// needs of the negative binomial: g-hat, nbar and the beta derivative
+// psi(n + beta) - psi(beta) - ln(1 + nbar/beta) + (nbar - n)/(beta + nbar);
+// G = sum g-hat then comes from the same float64 values.
 __global__ __launch_bounds__(256) void likelihood_kernel(LikeArgs a) {
   __shared__ double red[4];
   const long long c = blockIdx.y;
   const long long nv = a.nv;
-  const float lnc = (float)a.scal[c * kScalStride + kScalLnC];
+  const double lncd = a.scal[c * kScalStride + kScalLnC];
+  const float lnc = (float)lncd;
   double sl = 0.0, sg = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x) {
     const float lf = a.logf[c * nv + i];
@@ -766,8 +782,37 @@ __global__ __launch_bounds__(256) void likelihood_kernel(LikeArgs a) {
     }
     const float fn = (float)n;
     sl += (double)(lg - (beta + fn) * l1p + fn * (lnb - logf(beta)));
-    sg += (double)(beta * (fn - nb) / (beta + nb));
     if (a.nbar) a.nbar[c * nv + i] = nb;
+    if (a.ghat) {
+      const double bd = beta, fd = fn;
+      const double nbd = exp(lncd + (double)lf);
+      const double ib = 1.0 / (bd + nbd);
+      const double l1pd = -log1p(-nbd * ib);                 // ln(1 + nbar/beta)
+      double dg = 0.0;
+      if (n <= 64) {
+        // sum of 1/(beta+m) over m < n, as fractions of up to 8 terms (one
+        // division each; the denominator (beta+64)^8 stays inside float64)
+        for (int m0 = 0; m0 < n; m0 += 8) {
+          double pq = 0.0, qq = 1.0;
+          const int m1 = min(n, m0 + 8);
+          for (int m = m0; m < m1; ++m) {
+            const double bm = bd + (double)m;
+            pq = fma(pq, bm, qq);
+            qq *= bm;
+          }
+          dg += pq / qq;
+        }
+      } else {
+        dg = nb_digamma_big(n, bd);
+      }
+      const double gh = bd * (fd - nbd) * ib;
+      a.ghat[c * nv + i] = (float)gh;
+      a.nbv[c * nv + i] = (float)nbd;
+      a.dbeta[c * nv + i] = (float)(dg - l1pd + (nbd - fd) * ib);
+      sg += gh;
+    } else {
+      sg += (double)(beta * (fn - nb) / (beta + nb));
+    }
   }
   const double s1 = block_sum(sl, red);
   const double s2 = block_sum(sg, red);
@@ -791,14 +836,14 @@ __global__ __launch_bounds__(256) void voxel_bwd_kernel(VoxelArgs a) {
   // column per instruction, which would otherwise fall in one LDS bank
   __shared__ float sp[R][257];
   __shared__ double sd[4][257];
-  __shared__ double sacc[256];
+  __shared__ __align__(16) float tab[NE];       // bias table in LDS (see voxel_fwd_kernel)
   const long long c = blockIdx.y;
   const long long nv = a.nv;
-  const float* tab = a.table + c * NE;
+  if (threadIdx.x < NE) tab[threadIdx.x] = a.table[c * NE + threadIdx.x];
+  __syncthreads();
   VoxelArgs b = a;
   for (int k = 0; k < 6 * W; ++k) b.tens[k] = a.tens[k] + c * nv;
   const double* sc = a.scal + c * kScalStride;
-  const double lnc = sc[kScalLnC];
   const double gcoef = sc[kScalG] / sc[kScalNtr];
   const int t = threadIdx.x;
   const int my_e = t % NE, my_g = t / NE;
@@ -812,43 +857,23 @@ __global__ __launch_bounds__(256) void voxel_bwd_kernel(VoxelArgs a) {
       v.run(b, tab, i, rho);
 #pragma unroll
       for (int r = 0; r < R; ++r) sp[r][t] = v.preg[r];
-      // float64 where the sums cancel: n-bar, the NB terms and d/d beta
-      const int n = a.counts[c * nv + i];
-      const double fn = (double)n;
-      const double beta = v.theta[3];
-      const double nb = exp(lnc + (double)v.logf);
-      const double l1p = log1p(nb / beta);
-      double dg = 0.0;
-      if (n <= 64) {
-        // sum of 1/(beta+m) over m < n, as fractions of up to 8 terms (one
-        // division each; the denominator (beta+64)^8 stays inside float64)
-        for (int m0 = 0; m0 < n; m0 += 8) {
-          double pq = 0.0, qq = 1.0;
-          const int m1 = min(n, m0 + 8);
-          for (int m = m0; m < m1; ++m) {
-            const double bm = beta + (double)m;
-            pq = fma(pq, bm, qq);
-            qq *= bm;
-          }
-          dg += pq / qq;
-        }
-      } else {
-        dg = nb_digamma_big(n, beta);
-      }
-      const double ghat = beta * (fn - nb) / (beta + nb);
-      const double af = ghat - gcoef * nb;                      // f dlogL/df
-      const double lnx = v.lnx, u = v.u, ellr = v.ellr;
-      dth[0] = af * lnx;
-      dth[1] = -af * u * ellr;
-      dth[2] = af * u * (double)v.theta[1] / (double)v.theta[2];
-      dth[3] = dg - l1p + (nb - fn) / (beta + nb);
-      const double dxv = af * ((double)v.theta[0] - (double)v.theta[1] * u) / (double)v.x;
-      a.drho[c * nv + i] = rho > a.x_floor ? (float)dxv : 0.f;
+      // f dlogL/df = g-hat - (G / N_tr) nbar, in float64 for the sums
+      const double af = (double)a.ghat[c * nv + i] - gcoef * (double)a.nbv[c * nv + i];
+      dth[0] = af * (double)v.lnx;
+      dth[1] = -af * (double)(v.u * v.ellr);
+      dth[2] = af * (double)(v.u * v.theta[1] / v.theta[2]);
+      dth[3] = (double)a.dbeta[c * nv + i];
+      const float dxv = (float)af * ((v.theta[0] - v.theta[1] * v.u) / v.x);
+      a.drho[c * nv + i] = rho > a.x_floor ? dxv : 0.f;
+      // the membership cotangents only need float precision
+      const float dt0 = (float)dth[0], dt1 = (float)dth[1], dt2 = (float)dth[2], dt3 = (float)dth[3];
       float dp[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        dp[r] = (float)(tab[r * 4 + 0] * dth[0] + tab[r * 4 + 1] * dth[1] + tab[r * 4 + 2] * dth[2] +
-                        tab[r * 4 + 3] * dth[3]);
+      for (int r = 0; r < R; ++r) {
+        const float4 tr = reinterpret_cast<const float4*>(tab)[r];
+        dp[r] = tr.x * dt0 + tr.y * dt1 + tr.z * dt2 + tr.w * dt3;
+        if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
       float dpw[W][4];
       if (W == 1) {
 #pragma unroll
@@ -896,6 +921,7 @@ __global__ __launch_bounds__(256) void voxel_bwd_kernel(VoxelArgs a) {
     }
     __syncthreads();
   }
+  double* sacc = &sd[0][0];   // free after the last pass
   sacc[t] = acc;
   __syncthreads();
   if (t < NE) {

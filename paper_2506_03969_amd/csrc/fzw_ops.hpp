@@ -63,6 +63,9 @@ struct VoxelArgs {
   float* logf;
   float* beta;
   float* drho;
+  const float* ghat;     // backward inputs from the likelihood pass (see LikeArgs)
+  const float* nbv;
+  const float* dbeta;
   double* partial;
   float x_floor, steep, lam_th;
   long long nv;
@@ -75,6 +78,11 @@ struct LikeArgs {
   const double* scal;
   double* partial;
   float* nbar;
+  // gradient precursors, written when ghat is set: g-hat = beta (n - nbar) /
+  // (beta + nbar), nbar, and d lnP / d beta, all formed in float64
+  float* ghat;
+  float* nbv;
+  float* dbeta;
   long long nv;
 };
 

@@ -92,6 +92,9 @@ struct Group {
   float* tens[12] = {};
   float* logf = nullptr;
   float* beta = nullptr;
+  float* ghat = nullptr;     // backward inputs formed by the likelihood pass
+  float* nbv = nullptr;
+  float* dbeta = nullptr;
   float* drho_dir = nullptr;
   float* drho = nullptr;
   float2* spec[kNSpec] = {};
@@ -261,6 +264,9 @@ void alloc_group(fzw_plan* p, Group& g) {
   for (int k = 0; k < 6 * p->W; ++k) g.tens[k] = dalloc<float>(p, nf);
   g.logf = dalloc<float>(p, nf);
   g.beta = dalloc<float>(p, nf);
+  g.ghat = dalloc<float>(p, nf);
+  g.nbv = dalloc<float>(p, nf);
+  g.dbeta = dalloc<float>(p, nf);
   g.drho_dir = dalloc<float>(p, nf);
   g.drho = dalloc<float>(p, nf);
   for (auto& s : g.spec) s = dalloc<float2>(p, nsp);
@@ -391,7 +397,8 @@ void zi(const Group& g, float2* const* in, float* const* out, int k, hipStream_t
 constexpr int X = 0, Y = 1, Z = 2, NONE = -1;
 
 // ------------------------------------------------------------- forward model
-void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, float* nbar, double* logl) {
+void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, float* nbar, double* logl,
+                   bool grad) {
   hipStream_t s = p->stream;
   const float invn3 = (float)(1.0 / ((double)g.nv));
   const float d1 = (float)p->cosmo.d1;
@@ -530,6 +537,11 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     la.scal = p->scal + (size_t)g.c0 * kScalStride;
     la.partial = p->partial;
     la.nbar = nbar ? nbar + p->chain_off[g.c0] : nullptr;
+    if (grad) {
+      la.ghat = g.ghat;
+      la.nbv = g.nbv;
+      la.dbeta = g.dbeta;
+    }
     la.nv = g.nv;
     {
       Timed tm(p, FZW_K_LIKE, (2.5 + (nbar ? 1 : 0)) * field_bytes(g));
@@ -560,6 +572,9 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
     va.counts = p->counts + p->chain_off[g.c0];
     va.scal = p->scal + (size_t)g.c0 * kScalStride;
     va.drho = g.drho_dir;
+    va.ghat = g.ghat;
+    va.nbv = g.nbv;
+    va.dbeta = g.dbeta;
     va.partial = p->partial;
     va.x_floor = (float)p->cosmo.x_floor;
     va.steep = (float)p->web.steepness;
@@ -681,13 +696,13 @@ void check_ready(fzw_plan* p) {
 
 void forward_all(fzw_plan* p, const float* nu, const float* bias, float* nbar, double* logl) {
   t_plan = p;
-  for (auto& g : p->groups) forward_group(p, g, nu + p->chain_off[g.c0], bias, nbar, logl);
+  for (auto& g : p->groups) forward_group(p, g, nu + p->chain_off[g.c0], bias, nbar, logl, false);
 }
 
 void value_and_grad_all(fzw_plan* p, const float* nu, const float* bias, double* logl, float* dnu, float* dbias) {
   t_plan = p;
   for (auto& g : p->groups) {
-    forward_group(p, g, nu + p->chain_off[g.c0], bias, nullptr, logl);
+    forward_group(p, g, nu + p->chain_off[g.c0], bias, nullptr, logl, true);
     adjoint_group(p, g, bias, dnu + p->chain_off[g.c0], dbias);
   }
 }
