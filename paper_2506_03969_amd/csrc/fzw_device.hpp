@@ -334,6 +334,34 @@ __device__ __forceinline__ float2 spec_eval(const SpecOp& op, const KVec& kv, fl
   return make_float2(op.re * m, op.im * m);
 }
 
+// A multiplier with no wave-number or table factor: a plain constant.
+__device__ __forceinline__ bool spec_is_const(const SpecOp& op) {
+  return op.ax[0] < 0 && op.tb[0] < 0 && op.tb[1] < 0;
+}
+
+// ------------------------------------------------------------ buffer access
+// Raw buffer loads and stores (gfx9 descriptor, 32-bit byte offsets).  A lane
+// offset of kBufOff is out of range for every descriptor made here (they span
+// less than 1 GiB): its loads return zero and its stores are dropped, so
+// masked lanes need no branch.  The per-element row offset goes in the
+// scalar offset, so an access costs no address arithmetic.
+using BufRsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kBufOff = 0x40000000;
+__device__ __forceinline__ BufRsrc buf_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ float2 buf_load2(BufRsrc r, int voff, int soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+  return make_float2(__int_as_float((int)v[0]), __int_as_float((int)v[1]));
+}
+__device__ __forceinline__ void buf_store2(BufRsrc r, int voff, int soff, float2 x) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  u32x2 v;
+  v[0] = (unsigned)__float_as_int(x.x);
+  v[1] = (unsigned)__float_as_int(x.y);
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+}
+
 // ------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -351,12 +351,15 @@ __host__ __device__ constexpr int xy4_cols() {
 // registers without spilling; multi-mix passes use the Stockham kernel.
 template <int N, int AXIS, int NMID>
 __global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1, 3) void xy4_pass_kernel(PassArgs a, const float2* __restrict__ twg) {
-  constexpr int N1 = F4<N>::N1, N2 = F4<N>::N2, MU = N2 / N1;
+  constexpr int N1 = F4<N>::N1, N2 = F4<N>::N2;
   constexpr int M = N / 2;
   constexpr int P = pitch_c<N>();
   constexpr int C = xy4_cols<N>();
   constexpr int NT = C * N1;
   constexpr int LSZ = f4_lds<N>() + 1;
+  constexpr long long RS = AXIS == 0 ? (long long)N * P : (long long)P;   // row stride (elements)
+  constexpr int ROWB = (int)(RS * 8);                                     // row stride (bytes)
+  constexpr int RANGE = (int)(((N - 1) * RS + C) * 8);                   // bytes one workgroup spans
   __shared__ float2 lds[C * LSZ];
   __shared__ float2 tw[N];
   const int t = threadIdx.x;
@@ -364,16 +367,19 @@ __global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1, 3) void xy4_pass_kernel(
   const int c0 = blockIdx.x * C;
   const int b = blockIdx.y;
   const long long chain = blockIdx.z;
-  const long long rstride = AXIS == 0 ? (long long)N * P : (long long)P;
   const bool valid = (c0 + c) <= M;
-  const long long base = chain * a.chain_stride + (AXIS == 0 ? (long long)b * P : (long long)b * N * P) + c0 + c;
+  const long long base = chain * a.chain_stride + (AXIS == 0 ? (long long)b * P : (long long)b * N * P) + c0;
+  // lane part of every offset; the row part (a compile-time constant per
+  // element) goes in the scalar offset
+  const int voff = valid ? (int)((j * RS + c) * 8) : kBufOff;
   for (int i = t; i < N; i += NT) tw[i] = twg[i];
   const int nb = freq_index(b, N);
   const int nz = valid ? c0 + c : 0;
   const int nyq = N / 2;
   float2* lcol = lds + c * LSZ;
-  // rows held in layout B (register u N1 + k1)
+  // rows held in layout B (register u N1 + k1): N2 (e % N1) + j + N1 (e / N1)
   auto rowB = [&](int e) { return N2 * (e % N1) + j + N1 * (e / N1); };
+  auto rowB_off = [&](int e) { return (N2 * (e % N1) + N1 * (e / N1)) * ROWB; };
 
   float2 mid[NMID][N2];
 #pragma unroll
@@ -383,64 +389,86 @@ __global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1, 3) void xy4_pass_kernel(
   __syncthreads();
 
   for (int i = 0; i < a.nin; ++i) {
-    const float2* src = a.in[i] + base;
+    const BufRsrc src = buf_rsrc(a.in[i] + base, RANGE);
     float2 val[N2];
     if (a.in_fft & (1u << i)) {
 #pragma unroll
-      for (int q = 0; q < N2; ++q) val[q] = valid ? src[(j + N1 * q) * rstride] : make_float2(0.f, 0.f);
+      for (int q = 0; q < N2; ++q) val[q] = buf_load2(src, voff, N1 * q * ROWB);
       fwd_A_to_B<N>(val, lcol, j, tw);
     } else {
 #pragma unroll
-      for (int e = 0; e < N2; ++e) val[e] = valid ? src[rowB(e) * rstride] : make_float2(0.f, 0.f);
+      for (int e = 0; e < N2; ++e) val[e] = buf_load2(src, voff, rowB_off(e));
     }
 #pragma unroll
     for (int m = 0; m < NMID; ++m) {
       const SpecOp op = a.A[m][i];
-      if (op.re != 0.f || op.im != 0.f) {
+      if (op.re == 0.f && op.im == 0.f) continue;
+      if (spec_is_const(op)) {
+        const float2 k = make_float2(op.re, op.im);
 #pragma unroll
-        for (int e = 0; e < N2; ++e) {
-          KVec kv;
-          const int nr = freq_index(rowB(e), N);
-          kv.n[0] = AXIS == 0 ? nr : 0;
-          kv.n[1] = AXIS == 0 ? nb : nr;
-          kv.n[2] = nz;
-          kv.n2 = kv.n[0] * kv.n[0] + kv.n[1] * kv.n[1] + nz * nz;
-          mid[m][e] = cadd(mid[m][e], cmul(spec_eval(op, kv, a.kf, nyq, a.tabs, a.tab_stride), val[e]));
-        }
+        for (int e = 0; e < N2; ++e) mid[m][e] = cadd(mid[m][e], cmul(k, val[e]));
+        continue;
+      }
+#pragma unroll
+      for (int e = 0; e < N2; ++e) {
+        KVec kv;
+        const int nr = freq_index(rowB(e), N);
+        kv.n[0] = AXIS == 0 ? nr : 0;
+        kv.n[1] = AXIS == 0 ? nb : nr;
+        kv.n[2] = nz;
+        kv.n2 = kv.n[0] * kv.n[0] + kv.n[1] * kv.n[1] + nz * nz;
+        mid[m][e] = cadd(mid[m][e], cmul(spec_eval(op, kv, a.kf, nyq, a.tabs, a.tab_stride), val[e]));
       }
     }
   }
 
   for (int o = 0; o < a.nout; ++o) {
     float2 val[N2];
-#pragma unroll
-    for (int e = 0; e < N2; ++e) val[e] = make_float2(0.f, 0.f);
+    bool have = false;
 #pragma unroll
     for (int m = 0; m < NMID; ++m) {
       const SpecOp op = a.B[o][m];
-      if (op.re != 0.f || op.im != 0.f) {
+      if (op.re == 0.f && op.im == 0.f) continue;
+      if (spec_is_const(op)) {
+        const float2 k = make_float2(op.re, op.im);
+        if (!have) {
 #pragma unroll
-        for (int e = 0; e < N2; ++e) {
-          KVec kv;
-          const int nr = freq_index(rowB(e), N);
-          kv.n[0] = AXIS == 0 ? nr : 0;
-          kv.n[1] = AXIS == 0 ? nb : nr;
-          kv.n[2] = nz;
-          kv.n2 = kv.n[0] * kv.n[0] + kv.n[1] * kv.n[1] + nz * nz;
-          val[e] = cadd(val[e], cmul(spec_eval(op, kv, a.kf, nyq, a.tabs, a.tab_stride), mid[m][e]));
+          for (int e = 0; e < N2; ++e) val[e] = (op.re == 1.f && op.im == 0.f) ? mid[m][e] : cmul(k, mid[m][e]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < N2; ++e) val[e] = cadd(val[e], cmul(k, mid[m][e]));
         }
+        have = true;
+        continue;
+      }
+      if (!have) {
+#pragma unroll
+        for (int e = 0; e < N2; ++e) val[e] = make_float2(0.f, 0.f);
+        have = true;
+      }
+#pragma unroll
+      for (int e = 0; e < N2; ++e) {
+        KVec kv;
+        const int nr = freq_index(rowB(e), N);
+        kv.n[0] = AXIS == 0 ? nr : 0;
+        kv.n[1] = AXIS == 0 ? nb : nr;
+        kv.n[2] = nz;
+        kv.n2 = kv.n[0] * kv.n[0] + kv.n[1] * kv.n[1] + nz * nz;
+        val[e] = cadd(val[e], cmul(spec_eval(op, kv, a.kf, nyq, a.tabs, a.tab_stride), mid[m][e]));
       }
     }
-    float2* dst = a.out[o] + base;
+    if (!have) {
+#pragma unroll
+      for (int e = 0; e < N2; ++e) val[e] = make_float2(0.f, 0.f);
+    }
+    const BufRsrc dst = buf_rsrc(a.out[o] + base, RANGE);
     if (a.out_fft & (1u << o)) {
       inv_B_to_A<N>(val, lcol, j, tw);
-      if (valid) {
 #pragma unroll
-        for (int q = 0; q < N2; ++q) dst[(j + N1 * q) * rstride] = val[q];
-      }
-    } else if (valid) {
+      for (int q = 0; q < N2; ++q) buf_store2(dst, voff, N1 * q * ROWB, val[q]);
+    } else {
 #pragma unroll
-      for (int e = 0; e < N2; ++e) dst[rowB(e) * rstride] = val[e];
+      for (int e = 0; e < N2; ++e) buf_store2(dst, voff, rowB_off(e), val[e]);
     }
   }
 }
