@@ -81,6 +81,44 @@ def copy_calibration(torch, gib=1, reps=5):
           flush=True)
 
 
+def _trajectory(w, steps, reps, torch, Plan, CosmoParams, WebParams, step_size=1e-5):
+    """Time graph-captured leapfrog trajectories of every chain of workload w
+    (ragged meshes allowed): returns ms per leapfrog step (one gradient of
+    every chain) over `reps` trajectories after one warm-up trajectory.  The
+    noise is an independent draw, far from the synthetic counts, where the
+    gradient is large: a small step keeps every timed state close to it."""
+    import numpy as np
+    import fzw_inputs as fi
+    plan = _plan(w, w.chains, Plan, CosmoParams, WebParams)
+    for c, ch in enumerate(w.chains):
+        plan.set_counts(c, torch.from_numpy(fi.timing_counts(ch).view(np.int16)).cuda())
+    mu, sig = fi.prior_arrays(w)
+    plan.set_sampling(fi.tie_array(w), mu, sig)
+    nu = torch.from_numpy(np.concatenate([fi.white_noise(ch, fi.ROLE_EVAL_NU).astype(np.float32).ravel()
+                                          for ch in w.chains])).cuda()
+    u = torch.from_numpy(np.stack([fi.free_start(w, ch) for ch in w.chains]).astype(np.float32)).cuda()
+    base = torch.from_numpy(np.stack([ch.bias for ch in w.chains]).astype(np.float32)).cuda()
+    g = np.random.default_rng(7)
+    p_nu = torch.from_numpy(g.standard_normal(nu.numel()).astype(np.float32)).cuda()
+    p_u = torch.from_numpy(g.standard_normal(tuple(u.shape)).astype(np.float32)).cuda()
+    minv = torch.ones_like(nu)
+    minv_u = torch.full_like(u, 1e-2)
+    step = torch.full((len(w.chains),), step_size, dtype=torch.float32, device="cuda")
+    plan.leapfrog(nu, u, p_nu, p_u, base, minv, minv_u, step, steps)     # capture + first replay
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(plan.stream)
+    for _ in range(reps):
+        plan.leapfrog(nu, u, p_nu, p_u, base, minv, minv_u, step, steps)
+    ev1.record(plan.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / (reps * steps)
+    del plan
+    torch.cuda.empty_cache()
+    return ms
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +127,8 @@ def main():
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-trajectories", action="store_true",
+                    help="skip the ragged 32-chain and the 512^3 leapfrog trajectories")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -178,7 +218,25 @@ def main():
         del pb
         torch.cuda.empty_cache()
 
+    # leapfrog trajectories (hipGraph per trajectory): 32 ragged chains, and 512^3
+    trajectories = None
+    if not args.no_trajectories:
+        trajectories = {}
+        for name in ("c3", "c4"):
+            wt = fi.workload(name)
+            ms = _trajectory(wt, wt.leapfrog_steps, 2, torch, Plan, CosmoParams, WebParams)
+            vox = sum(ch.n ** 3 for ch in wt.chains)
+            model = sum(fi.bytes_model(ch.n, wt.web.n_webs, leapfrog=True) for ch in wt.chains)
+            trajectories[name] = {
+                "chains": len(wt.chains), "meshes": sorted({ch.n for ch in wt.chains}),
+                "leapfrog_steps": wt.leapfrog_steps, "ms_per_leapfrog_step": ms,
+                "grads_per_s": len(wt.chains) * 1e3 / ms, "voxel_grads_per_s": vox * 1e3 / ms,
+                "model_GBps": model / (ms * 1e6), "hbm_frac_model": model / (ms * 1e6) / HBM_PEAK_GBS}
+            print("# %s trajectory: %d chains, %.3f ms per leapfrog step (%.1f grads/s, %.0f GB/s model)" % (
+                name, len(wt.chains), ms, len(wt.chains) * 1e3 / ms, model / (ms * 1e6)), file=sys.stderr, flush=True)
+
     cpu = None if args.no_cpu else cpu_baseline(w)
+    model_bytes = fi.bytes_model(n, w.web.n_webs)
     line = {
         "metric": "forward+adjoint logL grads/sec at 256^3 (FP32, batched vs single) + % HBM peak",
         "value": value,
@@ -197,6 +255,10 @@ def main():
                    "mesh": n, "box": ch.box, "chains": 1},
         "batched": batched,
         "cic_atomic": cic_atomic,
+        "model_bytes_per_grad": model_bytes,
+        "model_GBps": model_bytes / (ms_per_step * 1e6),
+        "hbm_frac_model": model_bytes / (ms_per_step * 1e6) / HBM_PEAK_GBS,
+        "trajectories": trajectories,
         "algorithmic_GBps_all_kernels": total_alg / (ms_per_step * 1e6),
         "hbm_frac_algorithmic": total_alg / (ms_per_step * 1e6) / HBM_PEAK_GBS,
         "kernel_classes": classes,

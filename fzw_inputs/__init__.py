@@ -246,9 +246,43 @@ def timing_counts(chain: Chain, smooth_cells: float = 1.5) -> np.ndarray:
     kz = np.fft.rfftfreq(n).astype(np.float32)
     k2 = k[:, None, None] ** 2 + k[None, :, None] ** 2 + kz[None, None, :] ** 2
     filt = np.exp(-0.5 * k2 * (2 * np.pi * smooth_cells) ** 2).astype(np.float32)
-    s = np.fft.irfftn(np.fft.rfftn(w) * filt, s=w.shape).astype(np.float32)
+    s = np.fft.irfftn(np.fft.rfftn(w) * filt, s=w.shape, axes=(0, 1, 2)).astype(np.float32)
     s /= s.std() + 1e-30
     lam = np.exp(s - 0.5)
     lam *= chain.mean_count / lam.mean()
     beta = float(chain.bias[0, COL_BETA])
     return gamma_poisson_counts(lam, np.full_like(lam, beta), g)
+
+
+def tie_array(w: Workload) -> np.ndarray:
+    """Free-parameter index of every bias-table entry ([R][4] flattened), -1
+    for the entries held fixed: the layout the sampling call takes."""
+    tie = -np.ones(w.n_regions * 4, dtype=np.int64)
+    for f, (regions, col) in enumerate(w.free):
+        for r in regions:
+            tie[r * 4 + col] = f
+    return tie
+
+
+def prior_arrays(w: Workload):
+    """Gaussian prior (mean, sigma) on the log of every free bias parameter."""
+    mu, sig = [], []
+    for regions, col in w.free:
+        if col == COL_BETA:
+            mu.append(PRIOR_MU_BETA), sig.append(PRIOR_SIGMA_BETA)
+        else:
+            mu.append(PRIOR_MU_ALPHA), sig.append(PRIOR_SIGMA_ALPHA)
+    return np.array(mu), np.array(sig)
+
+
+def free_start(w: Workload, chain: Chain) -> np.ndarray:
+    """Log of the free bias parameters of a chain (the sampled coordinates)."""
+    return np.log(np.array([chain.bias[r[0], c] for r, c in w.free]))
+
+
+def bytes_model(n: int, n_webs: int, leapfrog: bool = False) -> float:
+    """Algorithmic bytes of one forward + adjoint on an n^3 mesh: every 3-D FFT
+    one 4-byte read and one write per voxel, every other kernel its distinct
+    field inputs and outputs; (382 + 168 W) bytes per voxel, plus 20 per voxel
+    for the leapfrog update."""
+    return float(n) ** 3 * (382 + 168 * n_webs + (20 if leapfrog else 0))

@@ -1,0 +1,240 @@
+"""Parity and invariants at the full workload sizes, in the launch
+configuration the benchmark times.
+
+* 256^3 two-web workload: fields, log-likelihood and both gradients against
+  the FP64 oracle at a near-truth state.
+* Ragged batch (one 64^3, one 96^3 and one 128^3 chain in one plan, as in the
+  32-chain workload): every chain against the oracle, and a batched leapfrog
+  trajectory equal bit for bit to the per-chain trajectories.
+* 512^3: too large for the oracle, so properties that hold at any size: the
+  transform against numpy, mass conservation of the deposit, determinism,
+  agreement of the two likelihood paths, and central differences of the
+  FP64-reduced logL along the gradient (1e-3) and a random direction (2e-2).
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import fzw_inputs as fi
+from tests.helpers import mock_case
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+if not torch.cuda.is_available():  # pragma: no cover - collected on CPU hosts
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from tests.gpu_helpers import bias_entry_error, dev, dev_counts, host, plan_for, relnorm  # noqa: E402
+
+FIELD_TOL = 1e-5
+LOGL_TOL = 1e-4
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.timeout(900)
+def test_c2_full_size_against_oracle():
+    """256^3, two webs, 16 regions, RSD: the bench workload."""
+    from oracle import model as om
+    om.set_workers(16)
+    _say("c2 256^3: mock data (oracle forward at truth)")
+    w, m, nu_t, nu_e, counts = mock_case("c2")
+    ch = w.chains[0]
+    nu = fi.near_truth_noise(ch)
+    p = plan_for(w)
+    p.set_counts(0, dev_counts(counts))
+    bias = dev(ch.bias.reshape(1, -1, 4))
+    logl, dnu, dbias = p.value_and_grad(dev(nu.ravel()), bias)
+    lf, nbar = p.forward(dev(nu.ravel()), bias, want_nbar=True)
+    gpu = {"dl": host(p.get_field(0, 0)), "rho": host(p.get_field(0, 4)),
+           "f": np.exp(host(p.get_field(0, 5)).ravel()), "nbar": host(nbar),
+           "psi": np.stack([host(p.get_field(0, k)) for k in (1, 2, 3)]),
+           "T": [np.stack([host(p.get_field(0, 6 + 6 * wi + k)) for k in range(6)]) for wi in range(2)]}
+    g_l, g_lf = float(host(logl)[0]), float(host(lf)[0])
+    g_dnu = host(dnu).reshape(nu.shape)
+    g_db = host(dbias).reshape(ch.bias.shape)
+    _say("c2 256^3: oracle forward")
+    st = m.forward(nu, ch.bias, counts)
+    errs = {"delta_L": relnorm(gpu["dl"], st["dl"]), "psi": relnorm(gpu["psi"], st["psi"]),
+            "rho": relnorm(gpu["rho"], st["rho"]), "f": relnorm(gpu["f"], st["f"]),
+            "nbar": relnorm(gpu["nbar"], st["nbar"])}
+    for wi in range(2):
+        errs["T%d" % wi] = relnorm(gpu["T"][wi], np.stack(st["tens"][wi]))
+    errs["logL"] = abs(g_l - st["logl"]) / abs(st["logl"])
+    _say("c2 256^3 fields:", " ".join("%s=%.2e" % kv for kv in errs.items()))
+    _say("c2 256^3: oracle adjoint")
+    ref_dnu, ref_db = m.adjoint(st)
+    e_nu = relnorm(g_dnu, ref_dnu)
+    e_bn = relnorm(g_db, ref_db)
+    e_b = bias_entry_error(g_db, ref_db)
+    _say("c2 256^3 gradient: dnu=%.2e dbias norm=%.2e entry=%.2e" % (e_nu, e_bn, e_b))
+    assert g_l == g_lf
+    for k, v in errs.items():
+        assert v < (LOGL_TOL if k == "logL" else FIELD_TOL), (k, v)
+    assert np.all(np.isfinite(g_dnu)) and np.all(np.isfinite(g_db))
+    assert e_bn < 1e-4 and e_b < 1e-4
+    if e_nu >= 1e-4:
+        # the oracle's own conditioning floor: how far its gradient moves when
+        # its input is rounded to FP32 or perturbed at relative 5e-7 (tracers
+        # in nearly empty cells next to CIC cell faces); held to ten times it
+        _say("c2 256^3: oracle conditioning floor")
+        rng = np.random.default_rng(99)
+        floor = 0.0
+        for x in (nu.astype(np.float32).astype(np.float64), nu * (1 + 5e-7 * rng.standard_normal(nu.shape))):
+            _, gx, _ = m.value_and_grad(x, ch.bias, counts)
+            floor = max(floor, relnorm(gx, ref_dnu))
+            _say("c2 256^3: floor sample %.2e" % relnorm(gx, ref_dnu))
+        assert e_nu < 10 * floor, (e_nu, floor)
+
+
+def _ragged():
+    w = fi.workload("c3")
+    sel = [0, 12, 22]                      # 64^3, 96^3, 128^3
+    return w, sel
+
+
+@pytest.mark.timeout(600)
+def test_ragged_batch_against_oracle():
+    """One plan holding a 64^3, a 96^3 and a 128^3 chain (the mix of the
+    32-chain workload): each chain's logL and gradients against the oracle."""
+    from oracle import model as om
+    om.set_workers(16)
+    w, sel = _ragged()
+    cases = []
+    for c in sel:
+        _say("ragged: mock data for chain", c, "n =", w.chains[c].n)
+        ww, m, nu_t, nu_e, counts = mock_case("c3", None, None, c)
+        cases.append((ww.chains[c], m, fi.near_truth_noise(ww.chains[c]), counts))
+    p = plan_for(w, sel)
+    for i, (ch, m, nu, counts) in enumerate(cases):
+        p.set_counts(i, dev_counts(counts))
+    nu_all = dev(np.concatenate([nu.ravel() for _, _, nu, _ in cases]))
+    bias_all = dev(np.stack([ch.bias for ch, _, _, _ in cases]))
+    logl, dnu, dbias = p.value_and_grad(nu_all, bias_all)
+    gl, gd, gb = host(logl), host(dnu), host(dbias)
+    for i, (ch, m, nu, counts) in enumerate(cases):
+        ref_l, ref_dnu, ref_db = m.value_and_grad(nu, ch.bias, counts)
+        o = p.offsets[i]
+        g = gd[o:o + ch.n ** 3].reshape(nu.shape)
+        e_l = abs(gl[i] - ref_l) / abs(ref_l)
+        e_nu = relnorm(g, ref_dnu)
+        e_bn = relnorm(gb[i], ref_db)
+        _say("ragged chain n=%d: logL=%.2e dnu=%.2e dbias norm=%.2e" % (ch.n, e_l, e_nu, e_bn))
+        assert e_l < LOGL_TOL
+        assert e_nu < 1e-3 and e_bn < 1e-3
+
+
+@pytest.mark.timeout(600)
+def test_ragged_leapfrog_equals_per_chain():
+    """A graph-captured trajectory of the ragged batch moves every chain
+    exactly as a plan holding that chain alone does (bit for bit)."""
+    w, sel = _ragged()
+    chains = [w.chains[c] for c in sel]
+    wsel = dataclasses.replace(w, chains=chains)
+    mu, sig = fi.prior_arrays(w)
+    tie = fi.tie_array(w)
+    counts = [fi.timing_counts(ch) for ch in chains]
+    nus = [fi.white_noise(ch, fi.ROLE_EVAL_NU).astype(np.float32) for ch in chains]
+    g = np.random.default_rng(3)
+    pnus = [g.standard_normal(x.shape).astype(np.float32) for x in nus]
+    us = [fi.free_start(w, ch).astype(np.float32) for ch in chains]
+    pus = [g.standard_normal(u.shape).astype(np.float32) for u in us]
+    steps, eps = 3, 1e-3
+
+    def run(idx):
+        ww = dataclasses.replace(wsel, chains=[chains[i] for i in idx])
+        p = plan_for(ww)
+        p.set_sampling(tie, mu, sig)
+        for k, i in enumerate(idx):
+            p.set_counts(k, dev_counts(counts[i]))
+        nu = dev(np.concatenate([nus[i].ravel() for i in idx]))
+        pn = dev(np.concatenate([pnus[i].ravel() for i in idx]))
+        u = dev(np.stack([us[i] for i in idx]))
+        pu = dev(np.stack([pus[i] for i in idx]))
+        base = dev(np.stack([chains[i].bias for i in idx]))
+        minv = torch.ones_like(nu)
+        minv_u = torch.full_like(u, 1e-2)
+        step = dev(np.full(len(idx), eps))
+        h0, h1 = p.leapfrog(nu, u, pn, pu, base, minv, minv_u, step, steps)
+        return p, host(nu), host(u), host(h0), host(h1)
+
+    pb, nu_b, u_b, h0_b, h1_b = run([0, 1, 2])
+    _say("ragged leapfrog H0", h0_b, "H1", h1_b)
+    assert np.all(np.isfinite(h1_b))
+    for i in range(3):
+        ps, nu_s, u_s, h0_s, h1_s = run([i])
+        o = pb.offsets[i]
+        n3 = chains[i].n ** 3
+        assert np.array_equal(nu_b[o:o + n3], nu_s[:n3])
+        assert np.array_equal(u_b[i], u_s[0])
+        assert h0_b[i] == h0_s[0] and h1_b[i] == h1_s[0]
+
+
+@pytest.mark.timeout(900)
+def test_512_invariants():
+    """512^3 (the 20-step trajectory workload): transform against numpy, mass
+    conservation, determinism, likelihood paths, directional derivative."""
+    import scipy.fft as sfft
+    w = fi.workload("c4")
+    ch = w.chains[0]
+    n = ch.n
+    p = plan_for(w)
+    _say("512^3: transform against numpy")
+    rng = np.random.default_rng(512)
+    x = rng.standard_normal((n, n, n)).astype(np.float32)
+    got = p.fft_r2c(dev(x[None]))[0]
+    ref = sfft.rfftn(x.astype(np.float64), workers=16)
+    err = relnorm(got.cpu().numpy(), ref)
+    back = host(p.fft_c2r(got[None]))[0]
+    err2 = relnorm(back, x.astype(np.float64) * float(n) ** 3)
+    _say("512^3 fft r2c err=%.2e round trip err=%.2e" % (err, err2))
+    del got, ref, back
+    assert err < 2e-6 and err2 < 4e-6
+
+    _say("512^3: likelihood and gradient")
+    # data drawn from the model's own mean at the truth noise, and the check
+    # made at that noise (a self-consistency check: nothing here is compared
+    # with the oracle).  Away from it, e.g. at a 5% perturbation, tracers fall
+    # in cells that are nearly empty there, log f ~ -rho_th / x makes d/dx
+    # ~ 1/x^2 huge, and no finite step sees the first-order change (the 256^3
+    # gradient, which matches the oracle, behaves the same way there).
+    p.set_counts(0, dev_counts(fi.timing_counts(ch)))
+    nu = dev(fi.white_noise(ch, fi.ROLE_TRUTH_NU).astype(np.float32).ravel())
+    bias = dev(ch.bias[None])
+    _, nbar = p.forward(nu, bias, want_nbar=True)
+    nbar_h = host(nbar).reshape((n,) * 3)
+    counts = fi.gamma_poisson_counts(nbar_h, np.full_like(nbar_h, float(ch.bias[0, fi.COL_BETA])),
+                                     fi.rng_for(ch, fi.ROLE_DATA))
+    del nbar, nbar_h
+    p.set_counts(0, dev_counts(counts))
+    l1, g1, b1 = [t.clone() for t in p.value_and_grad(nu, bias)]
+    rho = p.get_field(0, 4).double()
+    mass = float(rho.sum())
+    del rho
+    l2, g2, b2 = p.value_and_grad(nu, bias)
+    lf = p.forward(nu, bias)
+    _say("512^3 logL=%.9e forward=%.9e mass rel err=%.2e" % (float(l1[0]), float(lf[0]), abs(mass - n ** 3) / n ** 3))
+    assert abs(mass - float(n) ** 3) < 1e-6 * float(n) ** 3
+    assert torch.equal(l1, l2) and torch.equal(g1, g2) and torch.equal(b1, b2)
+    assert float(lf[0]) == float(l1[0])
+    assert bool(torch.isfinite(g1).all()) and bool(torch.isfinite(b1).all())
+
+    # directional derivatives: central differences of the FP64-reduced logL,
+    # along the gradient (step 1e-2) and along a random direction (step 1e-3)
+    gd = g1 / g1.norm()
+    h = 1e-2
+    fd = (float(p.forward(nu + h * gd, bias)[0]) - float(p.forward(nu - h * gd, bias)[0])) / (2 * h)
+    an = float(g1.double().norm())
+    _say("512^3 along the gradient: FD %.6e adjoint %.6e rel %.2e" % (fd, an, abs(fd - an) / abs(an)))
+    assert abs(fd - an) < 1e-3 * abs(an)
+    d = torch.from_numpy(np.random.default_rng(5).standard_normal(n ** 3).astype(np.float32)).cuda()
+    h = 1e-3
+    fd = (float(p.forward(nu + h * d, bias)[0]) - float(p.forward(nu - h * d, bias)[0])) / (2 * h)
+    an = float(torch.dot(g1.double(), d.double()))
+    _say("512^3 random direction: FD %.6e adjoint %.6e rel %.2e" % (fd, an, abs(fd - an) / abs(an)))
+    assert abs(fd - an) < 2e-2 * abs(an)
