@@ -163,16 +163,18 @@ fzw_status fzw_fft_c2r(fzw_plan* plan, int n, int batch, const void* in_complex,
 enum { FZW_CIC_SORTED = 0, FZW_CIC_ATOMIC = 1 };
 fzw_status fzw_set_cic_method(fzw_plan* plan, int method);
 
-/* Kernel classes for per-launch timing. */
+/* Kernel classes for per-launch timing: each FFT class is one kernel. */
 enum {
-  FZW_K_ZPASS = 0,     /* z-axis real<->complex FFT passes */
-  FZW_K_XYPASS = 1,    /* strided x / y FFT passes with spectral multipliers */
-  FZW_K_CIC = 2,       /* cloud-in-cell deposit (sort + gather) and its adjoint */
-  FZW_K_LPT = 3,       /* 2LPT / spherical-collapse pointwise terms and adjoint */
-  FZW_K_VOXEL_FWD = 4, /* per-voxel web memberships and bias */
-  FZW_K_LIKE = 5,      /* negative-binomial likelihood pass */
-  FZW_K_VOXEL_BWD = 6, /* per-voxel adjoint of web, bias and likelihood */
-  FZW_K_COUNT = 7
+  FZW_K_ZR2C = 0,      /* z-axis real-to-complex FFT pass */
+  FZW_K_ZC2R = 1,      /* z-axis complex-to-real FFT pass */
+  FZW_K_YPASS = 2,     /* strided y FFT pass with spectral multipliers */
+  FZW_K_XPASS = 3,     /* strided x FFT pass with spectral multipliers */
+  FZW_K_CIC = 4,       /* cloud-in-cell deposit (sort + gather) and its adjoint */
+  FZW_K_LPT = 5,       /* 2LPT / spherical-collapse pointwise terms and adjoint */
+  FZW_K_VOXEL_FWD = 6, /* per-voxel web memberships and bias */
+  FZW_K_LIKE = 7,      /* negative-binomial likelihood pass */
+  FZW_K_VOXEL_BWD = 8, /* per-voxel adjoint of web, bias and likelihood */
+  FZW_K_COUNT = 9
 };
 /* Turn per-launch timing on (1) or off (0): every later launch of the plan's
  * kernels (outside HIP graphs) is bracketed by HIP events on the plan's

@@ -303,7 +303,7 @@ struct Pass {
 thread_local fzw_plan* t_plan = nullptr;   // plan whose stages are being enqueued
 
 void run_pass(const Group& g, int axis, Pass& ps, int nmid, hipStream_t s) {
-  Timed tm(t_plan, FZW_K_XYPASS, (ps.a.nin + ps.a.nout) * spec_bytes(g));
+  Timed tm(t_plan, axis == 0 ? FZW_K_XPASS : FZW_K_YPASS, (ps.a.nin + ps.a.nout) * spec_bytes(g));
   ps.a.nmid = nmid;
   ps.a.chain_stride = g.ns;
   ps.a.tabs = g.tabs;
@@ -385,11 +385,11 @@ void hessian_yf(const Group& g, float2* const* in6, float2* g2, float2* g1, floa
 }
 
 void zf(const Group& g, float* const* in, float2* const* out, int k, hipStream_t s) {
-  Timed tm(t_plan, FZW_K_ZPASS, k * (field_bytes(g) + spec_bytes(g)));
+  Timed tm(t_plan, FZW_K_ZR2C, k * (field_bytes(g) + spec_bytes(g)));
   launch_zpass_r2c(g.n, (const float* const*)in, out, k, g.nc, g.nv, g.ns, g.tw_half, g.tw_full, s);
 }
 void zi(const Group& g, float2* const* in, float* const* out, int k, hipStream_t s) {
-  Timed tm(t_plan, FZW_K_ZPASS, k * (field_bytes(g) + spec_bytes(g)));
+  Timed tm(t_plan, FZW_K_ZC2R, k * (field_bytes(g) + spec_bytes(g)));
   launch_zpass_c2r(g.n, (const float2* const*)in, out, k, g.nc, g.ns, g.nv, g.tw_half, g.tw_full, s);
 }
 

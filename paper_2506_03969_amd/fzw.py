@@ -19,7 +19,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfzw.so"
 _lib = None
 
 WEB_PHI, WEB_DELTA = 0, 1
-KERNEL_CLASSES = ("zpass", "xypass", "cic", "lpt", "voxel_fwd", "likelihood", "voxel_bwd")
+KERNEL_CLASSES = ("z_r2c", "z_c2r", "y_pass", "x_pass", "cic", "lpt", "voxel_fwd", "likelihood", "voxel_bwd")
 
 
 class FzwError(RuntimeError):
