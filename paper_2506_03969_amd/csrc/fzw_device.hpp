@@ -339,6 +339,19 @@ __device__ __forceinline__ bool spec_is_const(const SpecOp& op) {
   return op.ax[0] < 0 && op.tb[0] < 0 && op.tb[1] < 0;
 }
 
+// Smooth hinge of the spherical-collapse term: (a + sqrt(a^2 + tau^2)) / 2
+// and its derivative; the exact max(a, 0) when tau = 0.
+__device__ __forceinline__ void sc_hinge(float a, float tau, float& hv, float& hd) {
+  if (tau > 0.f) {
+    const float r = sqrtf(a * a + tau * tau);
+    hv = 0.5f * (a + r);
+    hd = 0.5f * (1.f + a / r);
+  } else {
+    hv = a > 0.f ? a : 0.f;
+    hd = a > 0.f ? 1.f : 0.f;
+  }
+}
+
 // ------------------------------------------------------------ buffer access
 // Raw buffer loads and stores (gfx9 descriptor, 32-bit byte offsets).  A lane
 // offset of kBufOff is out of range for every descriptor made here (they span

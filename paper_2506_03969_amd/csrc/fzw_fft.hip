@@ -248,11 +248,67 @@ __host__ __device__ constexpr int z4_lines() {
   return (kTile / (N / 2)) > N * N ? N * N : kTile / (N / 2);
 }
 
+// One z line of a four-step tile, thread j of its N1 threads.  Layout A of a
+// length-M complex line: register q holds element j + N1 q, i.e. the packed
+// reals 2 (j + N1 q) and 2 (j + N1 q) + 1 of the length-N real line.
+//
+// Half spectrum `row` (N/2 + 1 entries) -> packed reals v (layout A), through
+// the real-packing identity and one inverse length-M transform.
+template <int N>
+__device__ __forceinline__ void z4_c2r_line(const float2* row, float2* v, float2* ll, int j, const float2* twh,
+                                            const float2* twf) {
+  constexpr int M = N / 2;
+  constexpr int N1 = F4<M>::N1, N2 = F4<M>::N2, MU = N2 / N1;
+#pragma unroll
+  for (int u = 0; u < MU; ++u) {
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+      const int k = N2 * k1 + j + N1 * u;
+      float2 xk = row[k];
+      float2 xm = row[M - k];
+      if (k == 0) {
+        xk.y = 0.f;
+        xm.y = 0.f;
+      }
+      const float2 A = cadd(xk, cconj(xm));
+      const float2 B = csub(xk, cconj(xm));
+      const float2 cB = cmul(cconj(twf[k]), B);
+      v[u * N1 + k1] = make_float2(A.x - cB.y, A.y + cB.x);
+    }
+  }
+  inv_B_to_A<M>(v, ll, j, twh);
+}
+
+// Packed reals v (layout A) -> half spectrum `row` (N/2 + 1 entries).  Ends
+// with a barrier, so `ll` may be reused at once.
+template <int N>
+__device__ __forceinline__ void z4_r2c_line(float2* v, float2* ll, int j, const float2* twh, const float2* twf,
+                                            float2* row) {
+  constexpr int M = N / 2;
+  constexpr int N1 = F4<M>::N1, N2 = F4<M>::N2, MU = N2 / N1;
+  fwd_A_to_B<M>(v, ll, j, twh);
+  // natural order into LDS for the real-to-complex unpacking
+#pragma unroll
+  for (int u = 0; u < MU; ++u)
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) ll[N2 * k1 + j + N1 * u] = v[u * N1 + k1];
+  __syncthreads();
+  for (int k = j; k <= M; k += N1) {
+    const float2 zk = ll[k == M ? 0 : k];
+    const float2 zm = ll[k == 0 ? 0 : M - k];
+    const float2 A = cadd(zk, cconj(zm));
+    const float2 B = csub(zk, cconj(zm));
+    const float2 wB = cmul(twf[k], B);
+    row[k] = make_float2(0.5f * (A.x + wB.y), 0.5f * (A.y - wB.x));
+  }
+  __syncthreads();
+}
+
 template <int N>
 __global__ __launch_bounds__(z4_lines<N>() * F4<N / 2>::N1) void zpass4_r2c_kernel(ZArgs a, const float2* __restrict__ tw_half,
                                                                                const float2* __restrict__ tw_full) {
   constexpr int M = N / 2;
-  constexpr int N1 = F4<M>::N1, N2 = F4<M>::N2, MU = N2 / N1;
+  constexpr int N1 = F4<M>::N1, N2 = F4<M>::N2;
   constexpr int L = z4_lines<N>();
   constexpr int NT = L * N1;
   constexpr int LSZ = f4_lds<M>();
@@ -274,30 +330,14 @@ __global__ __launch_bounds__(z4_lines<N>() * F4<N / 2>::N1) void zpass4_r2c_kern
 #pragma unroll
   for (int q = 0; q < N2; ++q) v[q] = src[j + N1 * q];
   __syncthreads();
-  float2* ll = lds + l * LSZ;
-  fwd_A_to_B<M>(v, ll, j, twh);
-  // natural order into LDS for the real-to-complex unpacking
-#pragma unroll
-  for (int u = 0; u < MU; ++u)
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) ll[N2 * k1 + j + N1 * u] = v[u * N1 + k1];
-  __syncthreads();
-  float2* row = out + line * P;
-  for (int k = j; k <= M; k += N1) {
-    const float2 zk = ll[k == M ? 0 : k];
-    const float2 zm = ll[k == 0 ? 0 : M - k];
-    const float2 A = cadd(zk, cconj(zm));
-    const float2 B = csub(zk, cconj(zm));
-    const float2 wB = cmul(twf[k], B);
-    row[k] = make_float2(0.5f * (A.x + wB.y), 0.5f * (A.y - wB.x));
-  }
+  z4_r2c_line<N>(v, lds + l * LSZ, j, twh, twf, out + line * P);
 }
 
 template <int N>
 __global__ __launch_bounds__(z4_lines<N>() * F4<N / 2>::N1) void zpass4_c2r_kernel(ZArgs a, const float2* __restrict__ tw_half,
                                                                                const float2* __restrict__ tw_full) {
   constexpr int M = N / 2;
-  constexpr int N1 = F4<M>::N1, N2 = F4<M>::N2, MU = N2 / N1;
+  constexpr int N1 = F4<M>::N1, N2 = F4<M>::N2;
   constexpr int L = z4_lines<N>();
   constexpr int NT = L * N1;
   constexpr int LSZ = f4_lds<M>();
@@ -315,29 +355,133 @@ __global__ __launch_bounds__(z4_lines<N>() * F4<N / 2>::N1) void zpass4_c2r_kern
   for (int i = t; i < M; i += NT) twh[i] = tw_half[i];
   for (int i = t; i < N; i += NT) twf[i] = tw_full[i];
   __syncthreads();
-  const float2* row = in + line * P;
   float2 v[N2];
-#pragma unroll
-  for (int u = 0; u < MU; ++u) {
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-      const int k = N2 * k1 + j + N1 * u;
-      float2 xk = row[k];
-      float2 xm = row[M - k];
-      if (k == 0) {
-        xk.y = 0.f;
-        xm.y = 0.f;
-      }
-      const float2 A = cadd(xk, cconj(xm));
-      const float2 B = csub(xk, cconj(xm));
-      const float2 cB = cmul(cconj(twf[k]), B);
-      v[u * N1 + k1] = make_float2(A.x - cB.y, A.y + cB.x);
-    }
-  }
-  inv_B_to_A<M>(v, lds + l * LSZ, j, twh);
+  z4_c2r_line<N>(in + line * P, v, lds + l * LSZ, j, twh, twf);
   float2* dst = out + line * M;
 #pragma unroll
   for (int q = 0; q < N2; ++q) dst[j + N1 * q] = v[q];
+}
+
+// ------------------------------------------ z transforms fused with the LPT
+// Forward: the six Hessian spectra phi_ij of a z line are brought to real
+// space (and stored: the adjoint needs them) while S2 = sum_{i<j} (phi_ii
+// phi_jj - phi_ij^2) and delta_L = tr phi accumulate in registers; then
+// S2 and d_SC = 3 (sqrt(hinge(1 - 2 D1 delta_L / 3)) - 1) are transformed back
+// from the same registers (the inverse leaves them in the layout the forward
+// transform starts from).  Neither S2 nor d_SC ever exists in real space in
+// memory.  Order of the components: xx, yy, zz, xy, xz, yz.
+template <int N>
+__global__ __launch_bounds__(z4_lines<N>() * F4<N / 2>::N1) void lpt_fwd_z4_kernel(LptZArgs a, const float2* __restrict__ tw_half,
+                                                                               const float2* __restrict__ tw_full) {
+  constexpr int M = N / 2;
+  constexpr int N1 = F4<M>::N1, N2 = F4<M>::N2;
+  constexpr int L = z4_lines<N>();
+  constexpr int NT = L * N1;
+  constexpr int LSZ = f4_lds<M>();
+  constexpr int P = pitch_c<N>();
+  __shared__ float2 lds[L * LSZ];
+  __shared__ float2 twh[M];
+  __shared__ float2 twf[N];
+  const int t = threadIdx.x;
+  const int j = t % N1, l = t / N1;
+  const long long chain = blockIdx.z;
+  const long long line = (long long)blockIdx.x * L + l;
+  const long long soff = chain * a.spec_chain_stride + line * P;
+  const long long roff = chain * (a.field_chain_stride / 2) + line * M;
+  float2* ll = lds + l * LSZ;
+  for (int i = t; i < M; i += NT) twh[i] = tw_half[i];
+  for (int i = t; i < N; i += NT) twf[i] = tw_full[i];
+  __syncthreads();
+  float2 S[N2], D[N2], v[N2];
+  for (int c = 0; c < 6; ++c) {
+    z4_c2r_line<N>(a.sin[c] + soff, v, ll, j, twh, twf);
+    float2* dst = reinterpret_cast<float2*>(a.field[c]) + roff;
+#pragma unroll
+    for (int q = 0; q < N2; ++q) dst[j + N1 * q] = v[q];
+    if (c == 0) {
+#pragma unroll
+      for (int q = 0; q < N2; ++q) D[q] = v[q];
+    } else if (c == 1) {
+#pragma unroll
+      for (int q = 0; q < N2; ++q) {
+        S[q] = make_float2(D[q].x * v[q].x, D[q].y * v[q].y);
+        D[q] = cadd(D[q], v[q]);
+      }
+    } else if (c == 2) {
+#pragma unroll
+      for (int q = 0; q < N2; ++q) {
+        S[q] = make_float2(S[q].x + D[q].x * v[q].x, S[q].y + D[q].y * v[q].y);
+        D[q] = cadd(D[q], v[q]);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < N2; ++q) S[q] = make_float2(S[q].x - v[q].x * v[q].x, S[q].y - v[q].y * v[q].y);
+    }
+  }
+  z4_r2c_line<N>(S, ll, j, twh, twf, a.sout[0] + soff);
+  const float k = (2.f / 3.f) * a.d1;
+#pragma unroll
+  for (int q = 0; q < N2; ++q) {
+    float hv, hd;
+    sc_hinge(1.f - k * D[q].x, a.tau, hv, hd);
+    v[q].x = 3.f * (sqrtf(hv) - 1.f);
+    sc_hinge(1.f - k * D[q].y, a.tau, hv, hd);
+    v[q].y = 3.f * (sqrtf(hv) - 1.f);
+  }
+  z4_r2c_line<N>(v, ll, j, twh, twf, a.sout[1] + soff);
+}
+
+// Adjoint: the cotangent spectra of S2 and d_SC come to real space, the
+// stored phi give delta_L and the hinge derivative, and each phi_ij cotangent
+// is formed in registers and transformed straight to its spectrum:
+// d phi_ii = dS2 (delta_L - phi_ii) + d delta_L, d phi_ij = -2 dS2 phi_ij.
+template <int N>
+__global__ __launch_bounds__(z4_lines<N>() * F4<N / 2>::N1) void lpt_bwd_z4_kernel(LptZArgs a, const float2* __restrict__ tw_half,
+                                                                               const float2* __restrict__ tw_full) {
+  constexpr int M = N / 2;
+  constexpr int N1 = F4<M>::N1, N2 = F4<M>::N2;
+  constexpr int L = z4_lines<N>();
+  constexpr int NT = L * N1;
+  constexpr int LSZ = f4_lds<M>();
+  constexpr int P = pitch_c<N>();
+  __shared__ float2 lds[L * LSZ];
+  __shared__ float2 twh[M];
+  __shared__ float2 twf[N];
+  const int t = threadIdx.x;
+  const int j = t % N1, l = t / N1;
+  const long long chain = blockIdx.z;
+  const long long line = (long long)blockIdx.x * L + l;
+  const long long soff = chain * a.spec_chain_stride + line * P;
+  const long long roff = chain * (a.field_chain_stride / 2) + line * M;
+  float2* ll = lds + l * LSZ;
+  for (int i = t; i < M; i += NT) twh[i] = tw_half[i];
+  for (int i = t; i < N; i += NT) twf[i] = tw_full[i];
+  __syncthreads();
+  float2 G2[N2], GD[N2], D[N2], v[N2];
+  z4_c2r_line<N>(a.sin[0] + soff, G2, ll, j, twh, twf);
+  z4_c2r_line<N>(a.sin[1] + soff, GD, ll, j, twh, twf);
+  auto phi = [&](int c) { return reinterpret_cast<const float2*>(a.field[c]) + roff; };
+#pragma unroll
+  for (int q = 0; q < N2; ++q) D[q] = cadd(cadd(phi(0)[j + N1 * q], phi(1)[j + N1 * q]), phi(2)[j + N1 * q]);
+  const float k = (2.f / 3.f) * a.d1;
+#pragma unroll
+  for (int q = 0; q < N2; ++q) {
+    float hv, hd;
+    sc_hinge(1.f - k * D[q].x, a.tau, hv, hd);
+    GD[q].x = hv > 0.f ? -GD[q].x * a.d1 * hd * rsqrtf(hv) : 0.f;
+    sc_hinge(1.f - k * D[q].y, a.tau, hv, hd);
+    GD[q].y = hv > 0.f ? -GD[q].y * a.d1 * hd * rsqrtf(hv) : 0.f;
+  }
+  for (int c = 0; c < 6; ++c) {
+    const float2* src = phi(c);
+#pragma unroll
+    for (int q = 0; q < N2; ++q) {
+      const float2 x = src[j + N1 * q];
+      v[q] = c < 3 ? make_float2(G2[q].x * (D[q].x - x.x) + GD[q].x, G2[q].y * (D[q].y - x.y) + GD[q].y)
+                   : make_float2(-2.f * G2[q].x * x.x, -2.f * G2[q].y * x.y);
+    }
+    z4_r2c_line<N>(v, ll, j, twh, twf, a.sout[c] + soff);
+  }
 }
 
 // Strided x / y pass, four-step variant.  Tile: C columns x N rows; thread t
@@ -537,6 +681,28 @@ void launch_zpass_c2r(int n, const float2* const* in, float* const* out, int nar
   za.in_chain_stride = in_chain_stride;
   za.out_chain_stride = out_chain_stride;
   FZW_DISPATCH_N(n, zc2r, za, chains, tw_half, tw_full, s);
+}
+
+template <int N>
+static void lpt_z(bool fwd, const LptZArgs& a, int chains, const float2* twh, const float2* twf, hipStream_t s,
+                  bool& done) {
+  if constexpr (N != 96) {
+    constexpr int L = z4_lines<N>();
+    dim3 grid((N * N) / L, 1, (unsigned)chains);
+    dim3 block(L * F4<N / 2>::N1);
+    if (fwd) hipLaunchKernelGGL(lpt_fwd_z4_kernel<N>, grid, block, 0, s, a, twh, twf);
+    else hipLaunchKernelGGL(lpt_bwd_z4_kernel<N>, grid, block, 0, s, a, twh, twf);
+    done = true;
+  }
+}
+
+bool has_four_step_z(int n) { return n != 96; }
+
+bool launch_lpt_z(int n, bool fwd, const LptZArgs& a, int chains, const float2* tw_half, const float2* tw_full,
+                  hipStream_t s) {
+  bool done = false;
+  FZW_DISPATCH_N(n, lpt_z, fwd, a, chains, tw_half, tw_full, s, done);
+  return done;
 }
 
 template <int N>

@@ -44,10 +44,28 @@ struct PassArgs {
   float kf;                   // 2 pi / L
 };
 
+// The z transforms around the LPT pointwise step, fused with it (see
+// lpt_fwd_z4_kernel / lpt_bwd_z4_kernel).  Forward: sin = six phi_ij spectra,
+// field = the six phi_ij (written), sout = S2 and d_SC spectra.  Adjoint: sin
+// = dS2 and dd_SC spectra, field = phi_ij (read), sout = six d phi_ij spectra.
+struct LptZArgs {
+  const float2* sin[6];
+  float* field[6];
+  float2* sout[6];
+  long long spec_chain_stride;    // complex elements between chains
+  long long field_chain_stride;   // floats between chains
+  float d1, tau;
+};
+
 // Launchers (defined next to their kernels).
 void launch_zpass_r2c(int n, const float* const* in, float2* const* out, int narr, long long chains,
                       long long in_chain_stride, long long out_chain_stride, const float2* tw_half,
                       const float2* tw_full, hipStream_t s);
+// Meshes whose z passes use the register four-step kernels (all but 96).
+bool has_four_step_z(int n);
+// Returns false (and launches nothing) for meshes without the four-step z pass.
+bool launch_lpt_z(int n, bool fwd, const LptZArgs& a, int chains, const float2* tw_half, const float2* tw_full,
+                  hipStream_t s);
 void launch_zpass_c2r(int n, const float2* const* in, float* const* out, int narr, long long chains,
                       long long in_chain_stride, long long out_chain_stride, const float2* tw_half,
                       const float2* tw_full, hipStream_t s);

@@ -31,17 +31,6 @@ void launch_fill_f32(float* p, long long n, float v, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ LPT pointwise
-__device__ __forceinline__ void sc_hinge(float a, float tau, float& hv, float& hd) {
-  if (tau > 0.f) {
-    const float r = sqrtf(a * a + tau * tau);
-    hv = 0.5f * (a + r);
-    hd = 0.5f * (1.f + a / r);
-  } else {
-    hv = a > 0.f ? a : 0.f;
-    hd = a > 0.f ? 1.f : 0.f;
-  }
-}
-
 // 2LPT source S2 = sum_{i<j} (phi_ii phi_jj - phi_ij^2) and the spherical
 // collapse divergence 3 (sqrt(hinge(1 - 2 D1 delta_L / 3)) - 1), delta_L = tr phi.
 __global__ void lpt_fwd_kernel(LptArgs a) {

@@ -384,6 +384,25 @@ void hessian_yf(const Group& g, float2* const* in6, float2* g2, float2* g1, floa
   }
 }
 
+// The z transforms around the LPT pointwise step, fused with it.  Forward:
+// six phi_ij spectra `in` -> phi (stored) -> S2, d_SC spectra `out`[0..1].
+// Adjoint: dS2, dd_SC spectra `in`[0..1] and phi -> six d phi_ij spectra
+// `out`.  Returns false where the mesh has no fused kernel.
+bool lpt_z(fzw_plan* p, const Group& g, bool fwd, float2* const* in, float2* const* out, hipStream_t s) {
+  LptZArgs a{};
+  const int nin = fwd ? 6 : 2, nout = fwd ? 2 : 6;
+  for (int c = 0; c < nin; ++c) a.sin[c] = in[c];
+  for (int c = 0; c < 6; ++c) a.field[c] = g.phi[c];
+  for (int c = 0; c < nout; ++c) a.sout[c] = out[c];
+  a.spec_chain_stride = g.ns;
+  a.field_chain_stride = g.nv;
+  a.d1 = (float)p->cosmo.d1;
+  a.tau = (float)p->cosmo.tau_sc;
+  if (!has_four_step_z(g.n)) return false;
+  Timed tm(p, FZW_K_LPT, (nin + nout) * spec_bytes(g) + 6 * field_bytes(g));
+  return launch_lpt_z(g.n, fwd, a, g.nc, g.tw_half, g.tw_full, s);
+}
+
 void zf(const Group& g, float* const* in, float2* const* out, int k, hipStream_t s) {
   Timed tm(t_plan, FZW_K_ZR2C, k * (field_bytes(g) + spec_bytes(g)));
   launch_zpass_r2c(g.n, (const float* const*)in, out, k, g.nc, g.nv, g.ns, g.tw_half, g.tw_full, s);
@@ -424,10 +443,11 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     ps.a.B[2][0] = spec(invn3, 0.f, NONE, NONE, TAB_INVK2, NONE);
     run_pass(g, X, ps, 1, s);
     hessian_yi(g, sp[2], sp[3], sp[4], &sp[5], s);
-    zi(g, &sp[5], g.phi, 6, s);
   }
-  // 2LPT source and spherical-collapse divergence
-  {
+  // phi_ij to real space, 2LPT source and spherical-collapse divergence, and
+  // their spectra (one fused launch where the mesh has the four-step z pass)
+  if (!lpt_z(p, g, true, &sp[5], &sp[2], s)) {
+    zi(g, &sp[5], g.phi, 6, s);
     LptArgs la{};
     for (int c = 0; c < 6; ++c) la.phi[c] = g.phi[c];
     la.s2 = g.s2;
@@ -435,13 +455,15 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     la.d1 = d1;
     la.tau = (float)p->cosmo.tau_sc;
     la.n = (long long)g.nc * g.nv;
-    Timed tm(p, FZW_K_LPT, 8 * field_bytes(g));
-    launch_lpt_fwd(la, s);
+    {
+      Timed tm(p, FZW_K_LPT, 8 * field_bytes(g));
+      launch_lpt_fwd(la, s);
+    }
+    float* src[2] = {g.s2, g.dsc};
+    zf(g, src, &sp[2], 2, s);
   }
   // ALPT blend -> Psi (Section 2.3)
   {
-    float* src[2] = {g.s2, g.dsc};
-    zf(g, src, &sp[2], 2, s);
     pure_pass(g, Y, false, &sp[2], 2, s);
     Pass ps;
     ps.in(sp[2], true).in(sp[3], true).in(sp[1], false);
@@ -652,11 +674,13 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
     ps.a.B[2][0] = spec(d1, 0.f, NONE, NONE, TAB_H, TAB_K);   // direct d nu_k (times N^3)
     run_pass(g, X, ps, 1, s);
     pure_pass(g, Y, true, &sp[2], 2, s);
+  }
+  // LPT pointwise adjoint and the spectra of the phi cotangents (one fused
+  // launch where the mesh has the four-step z pass; otherwise d phi is formed
+  // in place over phi)
+  if (!lpt_z(p, g, false, &sp[2], &sp[5], s)) {
     float* dst[2] = {g.s2, g.dsc};
     zi(g, &sp[2], dst, 2, s);
-  }
-  // LPT pointwise adjoint (d phi in place over phi)
-  {
     LptArgs la{};
     for (int c = 0; c < 6; ++c) {
       la.phi[c] = g.phi[c];
@@ -667,12 +691,14 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
     la.d1 = d1;
     la.tau = (float)p->cosmo.tau_sc;
     la.n = (long long)g.nc * g.nv;
-    Timed tm(p, FZW_K_LPT, 14 * field_bytes(g));
-    launch_lpt_bwd(la, s);
+    {
+      Timed tm(p, FZW_K_LPT, 14 * field_bytes(g));
+      launch_lpt_bwd(la, s);
+    }
+    zf(g, g.phi, &sp[5], 6, s);
   }
   // d nu_k = h / k^2 sum_ij k_i k_j rfft(d phi_ij) + direct ALPT term
   {
-    zf(g, g.phi, &sp[5], 6, s);
     hessian_yf(g, &sp[5], sp[5], sp[6], sp[7], s);
     Pass ps;
     ps.in(sp[5], true).in(sp[6], true).in(sp[7], true).in(sp[4], false);
