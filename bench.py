@@ -143,7 +143,7 @@ def main():
         copy_calibration(torch)
         return
     import fzw_inputs as fi
-    from paper_2506_03969_amd import CosmoParams, Plan, WebParams
+    from paper_2506_03969_amd import CosmoParams, Plan, WebParams, fft_schedule
 
     w = fi.workload(args.workload)
     ch = w.chains[0]
@@ -154,6 +154,8 @@ def main():
     counts_h = fi.timing_counts(ch)
     plan = _plan(w, [ch], Plan, CosmoParams, WebParams)
     plan.set_counts(0, torch.from_numpy(counts_h.view(np.int16)).cuda())
+    schedule = {k: {"family": v[0], "us_four_step": v[1], "us_alternative": v[2]}
+                for k, v in fft_schedule(n).items()}
     nu = torch.from_numpy(nu_h.ravel()).cuda()
     bias = torch.from_numpy(ch.bias.astype(np.float32)[None]).cuda()
     out = (torch.empty(1, dtype=torch.float64, device="cuda"), torch.empty_like(nu), torch.empty_like(bias))
@@ -262,6 +264,7 @@ def main():
         "algorithmic_GBps_all_kernels": total_alg / (ms_per_step * 1e6),
         "hbm_frac_algorithmic": total_alg / (ms_per_step * 1e6) / HBM_PEAK_GBS,
         "kernel_classes": classes,
+        "fft_schedule": schedule,
         "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "avg_launch_us": 1e3 * dom_ms / dom_n},

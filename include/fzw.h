@@ -163,6 +163,28 @@ fzw_status fzw_fft_c2r(fzw_plan* plan, int n, int batch, const void* in_complex,
 enum { FZW_CIC_SORTED = 0, FZW_CIC_ATOMIC = 1 };
 fzw_status fzw_set_cic_method(fzw_plan* plan, int method);
 
+/* FFT kernel schedule of a mesh size (process-wide).  The first plan created
+ * for a mesh size times, on its own buffers, the two kernel families of each
+ * pass type -- register four-step (0) and LDS Stockham (1) for the z passes
+ * and the mixing x/y passes; persistent four-step (0) or the mixing kernel (1)
+ * for pure x/y transforms -- and keeps the four-step kernels unless the
+ * alternative is at least 10% faster.  Every later plan of that size uses the
+ * same kernels, so results of plans in one process are comparable bit for
+ * bit.  The environment variable FZW_FFT_TUNE=0 keeps the defaults.
+ *   z, xy, pure: the chosen family per pass type (0 or 1);
+ *   us6 (nullable): measured microseconds per launch, [z, xy, pure] x
+ *     [four-step, alternative] (0 where a family does not exist for the size).
+ * Returns FZW_E_STATE while no plan of that size has been created, FZW_E_ARG
+ * for an unsupported size.  Never touches the GPU. */
+fzw_status fzw_fft_schedule(int mesh_n, int* z, int* xy, int* pure, double* us6);
+/* Set the schedule of a mesh size by hand (each 0 or 1 as above; the tuner
+ * then leaves it alone).  Applies to later launches of every plan; a HIP
+ * graph captured before keeps the kernels it was captured with.  The 96 mesh
+ * has only the Stockham z passes and x/y passes, and the 512 mesh only the
+ * Stockham x/y passes, whatever is set.  FZW_E_ARG for an unsupported size or
+ * a value other than 0 or 1. */
+fzw_status fzw_set_fft_schedule(int mesh_n, int z, int xy, int pure);
+
 /* Kernel classes for per-launch timing: each FFT class is one kernel. */
 enum {
   FZW_K_ZR2C = 0,      /* z-axis real-to-complex FFT pass */

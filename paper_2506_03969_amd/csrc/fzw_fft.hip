@@ -10,6 +10,8 @@
 // the tile back; the strided passes also apply spectral multipliers and mix
 // several inputs/outputs so that pointwise spectral work costs no extra pass.
 // Transforms are unnormalised in both directions (inverse = N^3 x).
+#include <algorithm>
+
 #include "fzw_device.hpp"
 
 namespace fzw {
@@ -617,29 +619,128 @@ __global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1, 3) void xy4_pass_kernel(
   }
 }
 
+// Pure strided transforms (no multiplier, one output per input, possibly in
+// place): the passes that only carry an array along one axis.  Persistent:
+// the grid is sized so that every workgroup walks the same number of column
+// groups (group = array, chain, fixed index of the other transverse axis,
+// column block), and the loads of the next group are issued before the
+// transform of the current one, so each workgroup keeps memory busy while it
+// computes.  Registers: the current and the prefetched column (2 x N2
+// complex) plus the transform.
+template <int N, int AXIS, bool INV>
+__global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1) void xy4_pure_kernel(PureArgs a, const float2* __restrict__ twg,
+                                                                           int ngroups) {
+  constexpr int N1 = F4<N>::N1, N2 = F4<N>::N2;
+  constexpr int M = N / 2;
+  constexpr int P = pitch_c<N>();
+  constexpr int C = xy4_cols<N>();
+  constexpr int NT = C * N1;
+  constexpr int NCG = (M + 1 + C - 1) / C;
+  constexpr int LSZ = f4_lds<N>() + 1;
+  constexpr long long RS = AXIS == 0 ? (long long)N * P : (long long)P;
+  constexpr int ROWB = (int)(RS * 8);
+  constexpr int RANGE = (int)(((N - 1) * RS + C) * 8);
+  __shared__ float2 lds[C * LSZ];
+  __shared__ float2 tw[N];
+  const int t = threadIdx.x;
+  const int c = t % C, j = t / C;
+  for (int i = t; i < N; i += NT) tw[i] = twg[i];
+  float2* lcol = lds + c * LSZ;
+  const int lane_off = (int)((j * RS + c) * 8);
+  // the input is in layout A for a forward transform, B for an inverse; the
+  // output in the other one
+  auto in_off = [&](int e) { return INV ? (N2 * (e % N1) + N1 * (e / N1)) * ROWB : N1 * e * ROWB; };
+  auto out_off = [&](int e) { return INV ? N1 * e * ROWB : (N2 * (e % N1) + N1 * (e / N1)) * ROWB; };
+  struct Where {
+    long long base;
+    int arr;
+    bool valid;
+  };
+  auto where = [&](int g) {
+    const int cg = g % NCG;
+    const int b = (g / NCG) % N;
+    const int ac = g / (NCG * N);
+    const int arr = ac / a.chains;
+    const long long chain = ac % a.chains;
+    Where w;
+    w.base = chain * a.chain_stride + (AXIS == 0 ? (long long)b * P : (long long)b * N * P) + cg * C;
+    w.arr = arr;
+    w.valid = cg * C + c <= M;
+    return w;
+  };
+  auto load = [&](int g, float2* dst) {
+    const Where w = where(g);
+    const BufRsrc r = buf_rsrc(a.in[w.arr] + w.base, RANGE);
+    const int voff = w.valid ? lane_off : kBufOff;
+#pragma unroll
+    for (int e = 0; e < N2; ++e) dst[e] = buf_load2(r, voff, in_off(e));
+  };
+
+  int g = blockIdx.x;
+  float2 nxt[N2];
+  if (g < ngroups) load(g, nxt);
+  __syncthreads();
+  for (; g < ngroups; g += gridDim.x) {
+    float2 v[N2];
+#pragma unroll
+    for (int e = 0; e < N2; ++e) v[e] = nxt[e];
+    const int gn = g + gridDim.x;
+    if (gn < ngroups) load(gn, nxt);
+    if (INV) inv_B_to_A<N>(v, lcol, j, tw);
+    else fwd_A_to_B<N>(v, lcol, j, tw);
+    const Where w = where(g);
+    const BufRsrc r = buf_rsrc(a.out[w.arr] + w.base, RANGE);
+    const int voff = w.valid ? lane_off : kBufOff;
+#pragma unroll
+    for (int e = 0; e < N2; ++e) buf_store2(r, voff, out_off(e), v[e]);
+  }
+}
+
 // ------------------------------------------------------------- launchers
+// Kernel family per mesh size (process-wide; chosen by the plan's tuner).
+FftSchedule& fft_schedule(int n) {
+  static FftSchedule table[8];
+  switch (n) {
+    case 16: return table[0];
+    case 32: return table[1];
+    case 64: return table[2];
+    case 96: return table[3];
+    case 128: return table[4];
+    case 256: return table[5];
+    default: return table[6];
+  }
+}
+
 template <int N>
 static void zr2c(const ZArgs& za, long long chains, const float2* twh, const float2* twf, hipStream_t s) {
-  if constexpr (N == 96) {
+  if constexpr (N != 96) {
+    if (fft_schedule(N).z == kSchedFourStep) {
+      constexpr int L = z4_lines<N>();
+      dim3 grid((N * N) / L, 1, (unsigned)(za.narr * chains));
+      hipLaunchKernelGGL(zpass4_r2c_kernel<N>, grid, dim3(L * F4<N / 2>::N1), 0, s, za, twh, twf);
+      return;
+    }
+  }
+  {
     constexpr int L = zlines<N>();
     dim3 grid((N * N) / L, 1, (unsigned)(za.narr * chains));
     hipLaunchKernelGGL(zpass_r2c_kernel<N>, grid, dim3(kThreads), 0, s, za, twh, twf);
-  } else {
-    constexpr int L = z4_lines<N>();
-    dim3 grid((N * N) / L, 1, (unsigned)(za.narr * chains));
-    hipLaunchKernelGGL(zpass4_r2c_kernel<N>, grid, dim3(L * F4<N / 2>::N1), 0, s, za, twh, twf);
   }
 }
 template <int N>
 static void zc2r(const ZArgs& za, long long chains, const float2* twh, const float2* twf, hipStream_t s) {
-  if constexpr (N == 96) {
+  if constexpr (N != 96) {
+    if (fft_schedule(N).z == kSchedFourStep) {
+      constexpr int L = z4_lines<N>();
+      dim3 grid((N * N) / L, 1, (unsigned)(za.narr * chains));
+      hipLaunchKernelGGL(zpass4_c2r_kernel<N>, grid, dim3(L * F4<N / 2>::N1), 0, s, za, twh, twf);
+      return;
+    }
+  }
+  {
     constexpr int L = zlines<N>();
     dim3 grid((N * N) / L, 1, (unsigned)(za.narr * chains));
     hipLaunchKernelGGL(zpass_c2r_kernel<N>, grid, dim3(kThreads), 0, s, za, twh, twf);
-  } else {
-    constexpr int L = z4_lines<N>();
-    dim3 grid((N * N) / L, 1, (unsigned)(za.narr * chains));
-    hipLaunchKernelGGL(zpass4_c2r_kernel<N>, grid, dim3(L * F4<N / 2>::N1), 0, s, za, twh, twf);
   }
 }
 
@@ -705,6 +806,83 @@ bool launch_lpt_z(int n, bool fwd, const LptZArgs& a, int chains, const float2* 
   return done;
 }
 
+// Workgroups of kernel `k` that fit on the device at once.
+static int resident_blocks(const void* k, int block) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, 0) != hipSuccess || cus <= 0 || per_cu <= 0) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return cus * per_cu;
+}
+
+template <int N, int AX, bool INV>
+static int& pure_capacity() {
+  static int cap = 0;
+  return cap;
+}
+
+template <int N, int AX, bool INV>
+static void pure_prime() {
+  int& cap = pure_capacity<N, AX, INV>();
+  if (cap == 0) {
+    cap = resident_blocks(reinterpret_cast<const void*>(&xy4_pure_kernel<N, AX, INV>), xy4_cols<N>() * F4<N>::N1);
+    if (cap <= 0) cap = 1024;   // a safe default: the kernel walks any number of groups
+  }
+}
+
+template <int N>
+static void pure4(int axis, bool inv, const PureArgs& a, const float2* tw, hipStream_t s, bool& done) {
+  if constexpr (N != 96 && N != 512) {
+    constexpr int block = xy4_cols<N>() * F4<N>::N1;
+    constexpr int NCG = (N / 2 + 1 + xy4_cols<N>() - 1) / xy4_cols<N>();
+    const int ngroups = NCG * N * a.chains * a.narr;
+    auto go = [&](auto kern, int cap) {
+      // equal work per workgroup: ceil(groups / capacity) groups each
+      const int per = (ngroups + cap - 1) / cap;
+      const int grid = (ngroups + per - 1) / per;
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, a, tw, ngroups);
+    };
+#define FZW_PURE(AX, INV)                                  \
+  do {                                                    \
+    pure_prime<N, AX, INV>();                             \
+    go(xy4_pure_kernel<N, AX, INV>, pure_capacity<N, AX, INV>()); \
+  } while (0)
+    if (axis == 0) {
+      if (inv) FZW_PURE(0, true);
+      else FZW_PURE(0, false);
+    } else {
+      if (inv) FZW_PURE(1, true);
+      else FZW_PURE(1, false);
+    }
+#undef FZW_PURE
+    done = true;
+  }
+}
+
+template <int N>
+static void pure_prime_all() {
+  if constexpr (N != 96 && N != 512) {
+    pure_prime<N, 0, false>();
+    pure_prime<N, 0, true>();
+    pure_prime<N, 1, false>();
+    pure_prime<N, 1, true>();
+  }
+}
+
+bool has_pure_pass(int n) { return n != 96 && n != 512; }
+
+bool launch_pure_pass(int n, int axis, bool inverse, const PureArgs& a, const float2* tw, hipStream_t s) {
+  if (fft_schedule(n).pure != kSchedFourStep) return false;
+  bool done = false;
+  FZW_DISPATCH_N(n, pure4, axis, inverse, a, tw, s, done);
+  return done;
+}
+
+void prime_launch_config(int n) { FZW_DISPATCH_N(n, pure_prime_all); }
+
 template <int N>
 static void xyp4(int axis, const PassArgs& a, int chains, const float2* tw, hipStream_t s) {
   constexpr int C = xy4_cols<N>();
@@ -719,7 +897,7 @@ static void xyp4(int axis, const PassArgs& a, int chains, const float2* tw, hipS
 template <int N>
 static void xyp(int axis, const PassArgs& a, int chains, const float2* tw, hipStream_t s) {
   if constexpr (N != 96 && N != 512) {
-    if (a.nmid == 1) {
+    if (a.nmid == 1 && fft_schedule(N).xy == kSchedFourStep) {
       xyp4<N>(axis, a, chains, tw, s);
       return;
     }

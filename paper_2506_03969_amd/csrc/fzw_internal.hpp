@@ -57,10 +57,39 @@ struct LptZArgs {
   float d1, tau;
 };
 
+// Pure strided transforms of narr arrays (out[i] may equal in[i]).
+struct PureArgs {
+  const float2* in[8];
+  float2* out[8];
+  int narr, chains;
+  long long chain_stride;   // complex elements between chains
+};
+
+// Kernel family of each pass type for one mesh size: the register four-step
+// kernels or the LDS Stockham kernels (z passes, mixing x/y passes), and for
+// pure x/y transforms the persistent four-step kernel or the mixing kernel.
+// Process-wide, so every plan computes with the same kernels; chosen by
+// timing when the first plan of a mesh size is created.
+enum { kSchedFourStep = 0, kSchedStockham = 1 };
+struct FftSchedule {
+  int z = kSchedFourStep, xy = kSchedFourStep, pure = kSchedFourStep;
+  bool tuned = false;
+  double us[3][2] = {};   // measured [z, xy, pure][four-step, alternative] per launch
+};
+FftSchedule& fft_schedule(int n);
+
 // Launchers (defined next to their kernels).
 void launch_zpass_r2c(int n, const float* const* in, float2* const* out, int narr, long long chains,
                       long long in_chain_stride, long long out_chain_stride, const float2* tw_half,
                       const float2* tw_full, hipStream_t s);
+// Pure x (axis 0) or y (axis 1) transforms, forward or inverse, of several
+// arrays in one persistent launch.  Returns false (nothing launched) for
+// meshes without the four-step strided kernels.
+bool launch_pure_pass(int n, int axis, bool inverse, const PureArgs& a, const float2* tw, hipStream_t s);
+bool has_pure_pass(int n);
+// Occupancy queries of the persistent kernels, made once per mesh size
+// before any stream capture.
+void prime_launch_config(int n);
 // Meshes whose z passes use the register four-step kernels (all but 96).
 bool has_four_step_z(int n);
 // Returns false (and launches nothing) for meshes without the four-step z pass.

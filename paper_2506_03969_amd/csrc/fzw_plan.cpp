@@ -2,6 +2,9 @@
 // tables, the stage schedule of the forward model and of its adjoint, the
 // leapfrog trajectory (captured as a HIP graph) and the C ABI of fzw.h.
 #include <hip/hip_runtime.h>
+#include <cstdlib>
+#include <mutex>
+#include <functional>
 
 #include <cmath>
 #include <cstdio>
@@ -312,27 +315,46 @@ void run_pass(const Group& g, int axis, Pass& ps, int nmid, hipStream_t s) {
   launch_xy_pass(g.n, axis, ps.a, g.nc, g.tw_full, s);
 }
 
-// pure forward or inverse transform of k arrays along an axis, in place
-// (one launch per array: every strided pass carries a single mix slot)
-void pure_pass(const Group& g, int axis, bool inverse, float2* const* arr, int k, hipStream_t s) {
+// Pure forward or inverse transforms along an axis: out[i] = F(in[i]) (in
+// place when out[i] == in[i]; no other aliasing).  One persistent launch for
+// all arrays where the mesh has the four-step kernels, else one mixing pass
+// per array.
+void pure_xy(const Group& g, int axis, bool inverse, float2* const* in, float2* const* out, int k, hipStream_t s) {
+  if (k <= 8) {
+    PureArgs pa{};
+    for (int i = 0; i < k; ++i) {
+      pa.in[i] = in[i];
+      pa.out[i] = out[i];
+    }
+    pa.narr = k;
+    pa.chains = g.nc;
+    pa.chain_stride = g.ns;
+    if (has_pure_pass(g.n)) {
+      Timed tm(t_plan, axis == 0 ? FZW_K_XPASS : FZW_K_YPASS, 2.0 * k * spec_bytes(g));
+      if (launch_pure_pass(g.n, axis, inverse, pa, g.tw_full, s)) return;
+    }
+  }
   for (int i = 0; i < k; ++i) {
     Pass ps;
-    ps.in(arr[i], !inverse).out(arr[i], inverse);
+    ps.in(in[i], !inverse).out(out[i], inverse);
     ps.a.A[0][0] = spec_const(1.f);
     ps.a.B[0][0] = spec_const(1.f);
     run_pass(g, axis, ps, 1, s);
   }
 }
 
+// pure forward or inverse transform of k arrays along an axis, in place
+void pure_pass(const Group& g, int axis, bool inverse, float2* const* arr, int k, hipStream_t s) {
+  pure_xy(g, axis, inverse, arr, arr, k, s);
+}
+
 // Inverse y pass from the three x-pass outputs (factors k_x^2, k_x, 1 of a
 // Hessian k_i k_j m(k)) to the six tensor components xx, yy, zz, xy, xz, yz.
 void hessian_yi(const Group& g, float2* a2, float2* a1, float2* a0, float2* const* out6, hipStream_t s) {
   {
-    Pass p2;
-    p2.in(a2, false).out(out6[0], true);
-    p2.a.A[0][0] = spec_const(1.f);
-    p2.a.B[0][0] = spec_const(1.f);
-    run_pass(g, 1, p2, 1, s);
+    float2* i2[1] = {a2};
+    float2* o2[1] = {out6[0]};
+    pure_xy(g, 1, true, i2, o2, 1, s);
   }
   {
     Pass p1;
@@ -376,11 +398,9 @@ void hessian_yf(const Group& g, float2* const* in6, float2* g2, float2* g1, floa
     run_pass(g, 1, p1, 1, s);
   }
   {
-    Pass p2;
-    p2.in(in6[0], true).out(g2, false);
-    p2.a.A[0][0] = spec_const(1.f);
-    p2.a.B[0][0] = spec_const(1.f);
-    run_pass(g, 1, p2, 1, s);
+    float2* i2[1] = {in6[0]};
+    float2* o2[1] = {g2};
+    pure_xy(g, 1, false, i2, o2, 1, s);
   }
 }
 
@@ -715,6 +735,72 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
   }
 }
 
+// ------------------------------------------------------------ FFT tuner
+// Times the two kernel families of each FFT pass type on this group's own
+// buffers (contents irrelevant: zeroed first) and records the faster in the
+// process-wide schedule of the mesh size.  The register four-step kernels are
+// the default; an alternative replaces them only when it is at least 10%
+// faster, so choices do not flip on timing noise.  Runs once per mesh size
+// and process, at plan creation (never inside a stream capture).  Setting
+// FZW_FFT_TUNE=0 keeps the defaults.
+double time_launch_us(hipStream_t s, const std::function<void()>& f) {
+  constexpr int kReps = 4;
+  f();
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  HIPCHK(hipEventRecord(a, s));
+  for (int r = 0; r < kReps; ++r) f();
+  HIPCHK(hipEventRecord(b, s));
+  HIPCHK(hipEventSynchronize(b));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return 1e3 * ms / kReps;
+}
+
+std::mutex g_tune_mu;
+
+void tune_fft(fzw_plan* p, Group& g) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  FftSchedule& sc = fft_schedule(g.n);
+  if (sc.tuned) return;
+  sc.tuned = true;
+  const char* env = std::getenv("FZW_FFT_TUNE");
+  if (env && env[0] == '0') return;
+  hipStream_t s = p->stream;
+  HIPCHK(hipMemsetAsync(g.rho, 0, (size_t)g.nc * g.nv * sizeof(float), s));
+  for (int k = 0; k < 2; ++k) HIPCHK(hipMemsetAsync(g.spec[k], 0, (size_t)g.nc * g.ns * sizeof(float2), s));
+  float* fin[1] = {g.rho};
+  float2* sp0[1] = {g.spec[0]};
+  auto pick = [&](int& choice, double* us, const std::function<void()>& f) {
+    choice = kSchedFourStep;
+    us[0] = time_launch_us(s, f);
+    choice = kSchedStockham;
+    us[1] = time_launch_us(s, f);
+    choice = us[1] < 0.9 * us[0] ? kSchedStockham : kSchedFourStep;
+  };
+  if (has_four_step_z(g.n)) {
+    pick(sc.z, sc.us[0], [&] {
+      zf(g, fin, sp0, 1, s);
+      zi(g, sp0, fin, 1, s);
+    });
+  }
+  if (has_pure_pass(g.n)) {
+    // a mixing pass with an axis factor and a radial table (the general path)
+    pick(sc.xy, sc.us[1], [&] {
+      Pass ps;
+      ps.in(g.spec[0], true).out(g.spec[1], true);
+      ps.a.A[0][0] = spec(0.f, 1.f, Y, NONE, TAB_INVK2, NONE);
+      ps.a.B[0][0] = spec_const(1.f);
+      run_pass(g, Y, ps, 1, s);
+    });
+    pick(sc.pure, sc.us[2], [&] { pure_xy(g, Y, false, sp0, sp0, 1, s); });
+  }
+  HIPCHK(hipStreamSynchronize(s));
+}
+
 void check_ready(fzw_plan* p) {
   for (int c = 0; c < p->n_chains; ++c)
     if (!p->counts_set[c]) throw Error(FZW_E_STATE, "counts of chain " + std::to_string(c) + " not set");
@@ -821,6 +907,8 @@ fzw_status fzw_plan_create(fzw_plan** out, int n_chains, const int* mesh_n, cons
     for (auto& g : p->groups) {
       build_tables(p, g);
       alloc_group(p, g);
+      prime_launch_config(g.n);
+      tune_fft(p, g);
       part = std::max(part, (size_t)g.nc * g.nblk * (size_t)std::max(2, p->R * 4));
     }
     part = std::max<size_t>(part, 512);
@@ -1148,5 +1236,34 @@ size_t fzw_chain_offset(const fzw_plan* p, int chain) {
 }
 int fzw_n_regions(const fzw_plan* p) { return p ? p->R : 0; }
 size_t fzw_workspace_bytes(const fzw_plan* p) { return p ? p->ws_bytes : 0; }
+
+fzw_status fzw_set_fft_schedule(int mesh_n, int z, int xy, int pure) {
+  auto ok = [](int v) { return v == kSchedFourStep || v == kSchedStockham; };
+  if (!supported_n(mesh_n) || !ok(z) || !ok(xy) || !ok(pure)) {
+    g_last_error = "fzw_set_fft_schedule: bad argument";
+    return FZW_E_ARG;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  FftSchedule& sc = fft_schedule(mesh_n);
+  sc.z = z;
+  sc.xy = xy;
+  sc.pure = pure;
+  sc.tuned = true;
+  return FZW_OK;
+}
+
+fzw_status fzw_fft_schedule(int mesh_n, int* z, int* xy, int* pure, double* us6) {
+  if (!supported_n(mesh_n) || !z || !xy || !pure) {
+    g_last_error = "fzw_fft_schedule: bad argument";
+    return FZW_E_ARG;
+  }
+  const FftSchedule& sc = fft_schedule(mesh_n);
+  *z = sc.z;
+  *xy = sc.xy;
+  *pure = sc.pure;
+  if (us6)
+    for (int k = 0; k < 6; ++k) us6[k] = sc.us[k / 2][k % 2];
+  return sc.tuned ? FZW_OK : FZW_E_STATE;
+}
 
 }  // extern "C"

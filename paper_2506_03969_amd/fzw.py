@@ -65,6 +65,10 @@ def load_library(path: str = _LIB_PATH):
     lib.fzw_timing_enable.restype = ctypes.c_int
     lib.fzw_timing_read.argtypes = [vp, i, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(d)]
     lib.fzw_timing_read.restype = ctypes.c_int
+    lib.fzw_fft_schedule.argtypes = [i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(d)]
+    lib.fzw_fft_schedule.restype = ctypes.c_int
+    lib.fzw_set_fft_schedule.argtypes = [i, i, i, i]
+    lib.fzw_set_fft_schedule.restype = ctypes.c_int
     lib.fzw_chain_offset.argtypes = [vp, i]
     lib.fzw_chain_offset.restype = sz
     lib.fzw_n_regions.argtypes = [vp]
@@ -256,6 +260,34 @@ class Plan:
         out = torch.empty((b, n, n, n), dtype=torch.float32, device=self.device)
         _check(_lib.fzw_fft_c2r(self._h, n, b, _ptr(x.contiguous(), torch.complex64), _ptr(out)), "fzw_fft_c2r")
         return out
+
+
+FFT_FAMILIES = ("four-step", "stockham")
+
+
+def fft_schedule(mesh_n: int):
+    """The FFT kernel schedule the library picked for a mesh size (after a
+    plan of that size exists): {'z', 'xy', 'pure'} -> (family, us four-step,
+    us alternative)."""
+    lib = load_library()
+    z, xy, pure = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    us = (ctypes.c_double * 6)()
+    _check(lib.fzw_fft_schedule(int(mesh_n), ctypes.byref(z), ctypes.byref(xy), ctypes.byref(pure), us),
+           "fzw_fft_schedule")
+    alt = {"z": "stockham", "xy": "stockham", "pure": "mixing"}
+    out = {}
+    for k, (name, v) in enumerate((("z", z.value), ("xy", xy.value), ("pure", pure.value))):
+        fam = "four-step" if v == 0 else alt[name]
+        out[name] = (fam, us[2 * k], us[2 * k + 1])
+    return out
+
+
+def set_fft_schedule(mesh_n: int, z: str = "four-step", xy: str = "four-step", pure: str = "four-step"):
+    """Force the FFT kernel families of a mesh size ('four-step' or the
+    alternative: 'stockham' for z and xy, 'mixing' for pure)."""
+    code = {"four-step": 0, "stockham": 1, "mixing": 1}
+    _check(load_library().fzw_set_fft_schedule(int(mesh_n), code[z], code[xy], code[pure]),
+           "fzw_set_fft_schedule")
 
 
 class LogLikelihood(torch.autograd.Function):

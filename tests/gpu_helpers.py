@@ -30,15 +30,4 @@ def host(t):
     return t.detach().double().cpu().numpy()
 
 
-def relnorm(x, ref):
-    x = np.asarray(x, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
-    return float(np.linalg.norm((x - ref).ravel()) / max(np.linalg.norm(ref.ravel()), 1e-300))
-
-
-def bias_entry_error(g, ref):
-    """max |g - ref| / max(|ref|, 1e-3 max|ref|) over the table entries."""
-    g = np.asarray(g, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
-    den = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
-    return float(np.max(np.abs(g - ref) / den))
+from tests.helpers import bias_entry_error, relnorm  # noqa: E402,F401  (numpy-only metrics)

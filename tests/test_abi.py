@@ -51,3 +51,21 @@ def test_plan_create_rejects_bad_arguments_without_gpu(lib):
     assert lib.fzw_plan_create(ctypes.byref(h), 1, n, box, ctypes.byref(cc), ctypes.byref(cw), None) == -1
     assert lib.fzw_plan_create(None, 1, n, box, ctypes.byref(cc), ctypes.byref(cw), None) == -1
     assert lib.fzw_forward(None, None, None, None, None) == -1
+
+
+def test_fft_schedule_query_and_validation_without_gpu(lib):
+    from paper_2506_03969_amd.fzw import load_library
+    lib = load_library(LIB)
+    z, xy, pure = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    us = (ctypes.c_double * 6)()
+    # unsupported size; bad family codes
+    assert lib.fzw_fft_schedule(100, ctypes.byref(z), ctypes.byref(xy), ctypes.byref(pure), us) == -1
+    assert lib.fzw_set_fft_schedule(64, 2, 0, 0) == -1
+    assert lib.fzw_set_fft_schedule(100, 0, 0, 0) == -1
+    # a size no plan has used yet: defaults (four-step), reported as not tuned
+    assert lib.fzw_fft_schedule(16, ctypes.byref(z), ctypes.byref(xy), ctypes.byref(pure), us) == -5
+    assert (z.value, xy.value, pure.value) == (0, 0, 0)
+    # setting by hand marks it as chosen
+    assert lib.fzw_set_fft_schedule(16, 1, 1, 0) == 0
+    assert lib.fzw_fft_schedule(16, ctypes.byref(z), ctypes.byref(xy), ctypes.byref(pure), None) == 0
+    assert (z.value, xy.value, pure.value) == (1, 1, 0)

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import fzw_inputs as fi
-from tests.helpers import mock_case
+from tests.helpers import mock_case, oracle_floor as _oracle_floor
 
 torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
@@ -100,25 +100,6 @@ def test_forward_stages_and_logl(case, which):
     for k, v in errs.items():
         tol = LOGL_TOL if k == "logL" else FIELD_TOL
         assert v < tol, (k, v)
-
-
-def _oracle_floor(m, nu, bias, counts, ref_dnu, ref_db):
-    """How far the FP64 gradient itself moves when its input is rounded to FP32
-    or perturbed at relative 5e-7 (the size of the error an FP32 path
-    accumulates over its ~10 FFT passes: its forward fields carry 2-9e-7):
-    the conditioning floor of any FP32 path.  Returns (d/dnu normwise, bias
-    per-entry) sensitivities."""
-    rng = np.random.default_rng(99)
-    fn, fb = 0.0, 0.0
-    # a few samples: the largest moves come from rare events (a particle
-    # crossing a CIC cell face next to a tracer-holding, nearly empty cell)
-    samples = [nu.astype(np.float32).astype(np.float64)]
-    samples += [nu * (1 + 5e-7 * rng.standard_normal(nu.shape)) for _ in range(4)]
-    for x in samples:
-        _, g, b = m.value_and_grad(x, bias, counts)
-        fn = max(fn, relnorm(g, ref_dnu))
-        fb = max(fb, bias_entry_error(b, ref_db))
-    return fn, fb
 
 
 GRAD_CASES = ([(c, "truth", None) for c in CASES] + [(c, "near", None) for c in CASES]
