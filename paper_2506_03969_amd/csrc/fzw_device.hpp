@@ -240,6 +240,7 @@ template <> struct F4<32>  { static constexpr int N1 = 4, N2 = 8; };
 template <> struct F4<64>  { static constexpr int N1 = 8, N2 = 8; };
 template <> struct F4<128> { static constexpr int N1 = 8, N2 = 16; };
 template <> struct F4<256> { static constexpr int N1 = 16, N2 = 16; };
+template <> struct F4<512> { static constexpr int N1 = 16, N2 = 32; };
 
 // LDS needed per line by the exchanges (rows padded by one element).
 template <int N>

@@ -835,7 +835,7 @@ static void pure_prime() {
 
 template <int N>
 static void pure4(int axis, bool inv, const PureArgs& a, const float2* tw, hipStream_t s, bool& done) {
-  if constexpr (N != 96 && N != 512) {
+  if constexpr (N != 96) {
     constexpr int block = xy4_cols<N>() * F4<N>::N1;
     constexpr int NCG = (N / 2 + 1 + xy4_cols<N>() - 1) / xy4_cols<N>();
     const int ngroups = NCG * N * a.chains * a.narr;
@@ -864,7 +864,7 @@ static void pure4(int axis, bool inv, const PureArgs& a, const float2* tw, hipSt
 
 template <int N>
 static void pure_prime_all() {
-  if constexpr (N != 96 && N != 512) {
+  if constexpr (N != 96) {
     pure_prime<N, 0, false>();
     pure_prime<N, 0, true>();
     pure_prime<N, 1, false>();
@@ -872,7 +872,7 @@ static void pure_prime_all() {
   }
 }
 
-bool has_pure_pass(int n) { return n != 96 && n != 512; }
+bool has_pure_pass(int n) { return n != 96; }
 
 bool launch_pure_pass(int n, int axis, bool inverse, const PureArgs& a, const float2* tw, hipStream_t s) {
   if (fft_schedule(n).pure != kSchedFourStep) return false;
@@ -896,7 +896,7 @@ static void xyp4(int axis, const PassArgs& a, int chains, const float2* tw, hipS
 
 template <int N>
 static void xyp(int axis, const PassArgs& a, int chains, const float2* tw, hipStream_t s) {
-  if constexpr (N != 96 && N != 512) {
+  if constexpr (N != 96) {
     if (a.nmid == 1 && fft_schedule(N).xy == kSchedFourStep) {
       xyp4<N>(axis, a, chains, tw, s);
       return;
