@@ -663,9 +663,8 @@ __device__ __forceinline__ double digamma_d(double x) {
 // Counts above 64 are rare: their lnGamma(n+beta) - lnGamma(beta) and
 // psi(n+beta) - psi(beta) use float64 special functions out of line (below
 // that the finite sums over m < n are used).
-__device__ __noinline__ float nb_lgamma_big(int n, float beta) {
-  const double b = beta;
-  return (float)(lgamma((double)n + b) - lgamma(b));
+__device__ __noinline__ double nb_lgamma_big_d(int n, double beta) {
+  return lgamma((double)n + beta) - lgamma(beta);
 }
 __device__ __noinline__ double nb_digamma_big(int n, double beta) {
   return digamma_d((double)n + beta) - digamma_d(beta);
@@ -744,63 +743,55 @@ __global__ __launch_bounds__(256) void voxel_fwd_kernel(VoxelArgs a) {
 }
 
 // Likelihood pass: needs ln C = ln N_tr - ln sum f from the reduced partials.
-// Per-voxel terms in FP32 (accurate library functions), sums in FP64.  With
-// ghat set it also forms, in float64 where the terms cancel, what the backward
-// needs of the negative binomial: g-hat, nbar and the beta derivative
-// psi(n + beta) - psi(beta) - ln(1 + nbar/beta) + (nbar - n)/(beta + nbar);
-// G = sum g-hat then comes from the same float64 values.
+// Per voxel in float64: nbar = exp(ln C + log f), ln(1 + nbar/beta), and the
+// finite sums over m < n of ln(beta + m) (lnGamma(n+beta) - lnGamma(beta))
+// and 1/(beta + m) (psi(n+beta) - psi(beta)) from one loop over the count
+// with the products of up to 8 factors (one logarithm and one division per 8
+// terms; (beta+64)^8 stays inside float64).  Sums in FP64.  With ghat set it
+// also writes what the backward needs: g-hat = beta (n - nbar)/(beta + nbar),
+// nbar, and d lnP/d beta = psi(n+beta) - psi(beta) - ln(1 + nbar/beta) +
+// (nbar - n)/(beta + nbar); G = sum g-hat comes from the same values.
 __global__ __launch_bounds__(256) void likelihood_kernel(LikeArgs a) {
   __shared__ double red[4];
   const long long c = blockIdx.y;
   const long long nv = a.nv;
-  const double lncd = a.scal[c * kScalStride + kScalLnC];
-  const float lnc = (float)lncd;
+  const double lnc = a.scal[c * kScalStride + kScalLnC];
+  const bool grad = a.ghat != nullptr;
   double sl = 0.0, sg = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x) {
     const float lf = a.logf[c * nv + i];
-    const float beta = a.beta[c * nv + i];
+    const double beta = a.beta[c * nv + i];
     const int n = a.counts[c * nv + i];
-    const float lnb = lnc + lf;
-    const float nb = expf(lnb);
-    const float l1p = log1pf(nb / beta);
-    float lg = 0.f;
+    const double fn = (double)n;
+    const double lnb = lnc + (double)lf;
+    const double nb = exp(lnb);
+    const double ib = 1.0 / (beta + nb);
+    const double l1p = -log1p(-nb * ib);                     // ln(1 + nbar/beta)
+    double lg = 0.0, dg = 0.0;
     if (n <= 64) {
-      for (int m = 0; m < n; ++m) lg += logf(beta + (float)m);
-    } else {
-      lg = nb_lgamma_big(n, beta);
-    }
-    const float fn = (float)n;
-    sl += (double)(lg - (beta + fn) * l1p + fn * (lnb - logf(beta)));
-    if (a.nbar) a.nbar[c * nv + i] = nb;
-    if (a.ghat) {
-      const double bd = beta, fd = fn;
-      const double nbd = exp(lncd + (double)lf);
-      const double ib = 1.0 / (bd + nbd);
-      const double l1pd = -log1p(-nbd * ib);                 // ln(1 + nbar/beta)
-      double dg = 0.0;
-      if (n <= 64) {
-        // sum of 1/(beta+m) over m < n, as fractions of up to 8 terms (one
-        // division each; the denominator (beta+64)^8 stays inside float64)
-        for (int m0 = 0; m0 < n; m0 += 8) {
-          double pq = 0.0, qq = 1.0;
-          const int m1 = min(n, m0 + 8);
-          for (int m = m0; m < m1; ++m) {
-            const double bm = bd + (double)m;
-            pq = fma(pq, bm, qq);
-            qq *= bm;
-          }
-          dg += pq / qq;
+      for (int m0 = 0; m0 < n; m0 += 8) {
+        double pq = 0.0, qq = 1.0;
+        const int m1 = min(n, m0 + 8);
+        for (int m = m0; m < m1; ++m) {
+          const double bm = beta + (double)m;
+          pq = fma(pq, bm, qq);
+          qq *= bm;
         }
-      } else {
-        dg = nb_digamma_big(n, bd);
+        lg += log(qq);
+        if (grad) dg += pq / qq;
       }
-      const double gh = bd * (fd - nbd) * ib;
-      a.ghat[c * nv + i] = (float)gh;
-      a.nbv[c * nv + i] = (float)nbd;
-      a.dbeta[c * nv + i] = (float)(dg - l1pd + (nbd - fd) * ib);
-      sg += gh;
     } else {
-      sg += (double)(beta * (fn - nb) / (beta + nb));
+      lg = nb_lgamma_big_d(n, beta);
+      if (grad) dg = nb_digamma_big(n, beta);
+    }
+    sl += lg - (beta + fn) * l1p + fn * (lnb - log(beta));
+    const double gh = beta * (fn - nb) * ib;
+    sg += gh;
+    if (a.nbar) a.nbar[c * nv + i] = (float)nb;
+    if (grad) {
+      a.ghat[c * nv + i] = (float)gh;
+      a.nbv[c * nv + i] = (float)nb;
+      a.dbeta[c * nv + i] = (float)(dg - l1p + (nb - fn) * ib);
     }
   }
   const double s1 = block_sum(sl, red);

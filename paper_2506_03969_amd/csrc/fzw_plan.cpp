@@ -896,7 +896,7 @@ fzw_status fzw_plan_create(fzw_plan** out, int n_chains, const int* mesh_n, cons
         g.nv = nv;
         g.P = spectrum_pitch(g.n);
         g.ns = (long long)g.n * g.n * g.P;
-        g.nblk = (int)std::min<long long>((nv + 255) / 256, 2048);
+        g.nblk = (int)std::min<long long>((nv + 255) / 256, 16384);
         p->groups.push_back(g);
       }
       p->chain_group.push_back((int)p->groups.size() - 1);
