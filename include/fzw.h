@@ -185,18 +185,24 @@ fzw_status fzw_fft_schedule(int mesh_n, int* z, int* xy, int* pure, double* us6)
  * a value other than 0 or 1. */
 fzw_status fzw_set_fft_schedule(int mesh_n, int z, int xy, int pure);
 
-/* Kernel classes for per-launch timing: each FFT class is one kernel. */
+/* Kernel classes for per-launch timing.  Every class but the CIC deposit is
+ * one kernel (at meshes with the four-step kernels; the pure classes are one
+ * kernel template with a forward and an inverse instance). */
 enum {
-  FZW_K_ZR2C = 0,      /* z-axis real-to-complex FFT pass */
-  FZW_K_ZC2R = 1,      /* z-axis complex-to-real FFT pass */
-  FZW_K_YPASS = 2,     /* strided y FFT pass with spectral multipliers */
-  FZW_K_XPASS = 3,     /* strided x FFT pass with spectral multipliers */
-  FZW_K_CIC = 4,       /* cloud-in-cell deposit (sort + gather) and its adjoint */
-  FZW_K_LPT = 5,       /* 2LPT / spherical-collapse pointwise terms and adjoint */
-  FZW_K_VOXEL_FWD = 6, /* per-voxel web memberships and bias */
-  FZW_K_LIKE = 7,      /* negative-binomial likelihood pass */
-  FZW_K_VOXEL_BWD = 8, /* per-voxel adjoint of web, bias and likelihood */
-  FZW_K_COUNT = 9
+  FZW_K_ZR2C = 0,        /* z-axis real-to-complex FFT pass */
+  FZW_K_ZC2R = 1,        /* z-axis complex-to-real FFT pass */
+  FZW_K_YMIX = 2,        /* strided y pass with spectral multipliers / mixing */
+  FZW_K_XMIX = 3,        /* strided x pass with spectral multipliers / mixing */
+  FZW_K_YPURE = 4,       /* pure y transforms (persistent kernel) */
+  FZW_K_XPURE = 5,       /* pure x transforms (persistent kernel) */
+  FZW_K_LPT_FWD = 6,     /* LPT pointwise step with its z transforms, forward */
+  FZW_K_LPT_BWD = 7,     /* the same, adjoint */
+  FZW_K_CIC_DEP = 8,     /* cloud-in-cell deposit (count, scan, scatter, gather) */
+  FZW_K_CIC_ADJ = 9,     /* cloud-in-cell adjoint */
+  FZW_K_VOXEL_FWD = 10,  /* per-voxel web memberships and bias */
+  FZW_K_LIKE = 11,       /* negative-binomial likelihood pass */
+  FZW_K_VOXEL_BWD = 12,  /* per-voxel adjoint of web, bias and likelihood */
+  FZW_K_COUNT = 13
 };
 /* Turn per-launch timing on (1) or off (0): every later launch of the plan's
  * kernels (outside HIP graphs) is bracketed by HIP events on the plan's

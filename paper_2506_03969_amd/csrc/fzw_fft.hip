@@ -534,17 +534,32 @@ __global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1, 3) void xy4_pass_kernel(
     for (int e = 0; e < N2; ++e) mid[m][e] = make_float2(0.f, 0.f);
   __syncthreads();
 
-  for (int i = 0; i < a.nin; ++i) {
+  // input i in registers: layout A rows when it is transformed here, else B
+  auto load_input = [&](int i, float2* dst) {
     const BufRsrc src = buf_rsrc(a.in[i] + base, RANGE);
-    float2 val[N2];
     if (a.in_fft & (1u << i)) {
 #pragma unroll
-      for (int q = 0; q < N2; ++q) val[q] = buf_load2(src, voff, N1 * q * ROWB);
-      fwd_A_to_B<N>(val, lcol, j, tw);
+      for (int q = 0; q < N2; ++q) dst[q] = buf_load2(src, voff, N1 * q * ROWB);
     } else {
 #pragma unroll
-      for (int e = 0; e < N2; ++e) val[e] = buf_load2(src, voff, rowB_off(e));
+      for (int e = 0; e < N2; ++e) dst[e] = buf_load2(src, voff, rowB_off(e));
     }
+  };
+  // with several inputs, the loads of input i+1 are in flight during the
+  // transform of input i
+  const bool pf = a.nin > 1;
+  float2 nxt[N2];
+  if (pf) load_input(0, nxt);
+  for (int i = 0; i < a.nin; ++i) {
+    float2 val[N2];
+    if (pf) {
+#pragma unroll
+      for (int e = 0; e < N2; ++e) val[e] = nxt[e];
+      if (i + 1 < a.nin) load_input(i + 1, nxt);
+    } else {
+      load_input(i, val);
+    }
+    if (a.in_fft & (1u << i)) fwd_A_to_B<N>(val, lcol, j, tw);
 #pragma unroll
     for (int m = 0; m < NMID; ++m) {
       const SpecOp op = a.A[m][i];
@@ -840,15 +855,13 @@ static void pure4(int axis, bool inv, const PureArgs& a, const float2* tw, hipSt
     constexpr int NCG = (N / 2 + 1 + xy4_cols<N>() - 1) / xy4_cols<N>();
     const int ngroups = NCG * N * a.chains * a.narr;
     auto go = [&](auto kern, int cap) {
-      // equal work per workgroup: ceil(groups / capacity) groups each
-      const int per = (ngroups + cap - 1) / cap;
-      const int grid = (ngroups + per - 1) / per;
-      hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, a, tw, ngroups);
+      const int per = (ngroups + cap - 1) / cap;   // equal work per workgroup
+      hipLaunchKernelGGL(kern, dim3((ngroups + per - 1) / per), dim3(block), 0, s, a, tw, ngroups);
     };
-#define FZW_PURE(AX, INV)                                  \
-  do {                                                    \
-    pure_prime<N, AX, INV>();                             \
-    go(xy4_pure_kernel<N, AX, INV>, pure_capacity<N, AX, INV>()); \
+#define FZW_PURE(AX, INV)                                            \
+  do {                                                              \
+    pure_prime<N, AX, INV>();                                       \
+    go(xy4_pure_kernel<N, AX, INV>, pure_capacity<N, AX, INV>());   \
   } while (0)
     if (axis == 0) {
       if (inv) FZW_PURE(0, true);
@@ -888,10 +901,8 @@ static void xyp4(int axis, const PassArgs& a, int chains, const float2* tw, hipS
   constexpr int C = xy4_cols<N>();
   dim3 grid((N / 2 + 1 + C - 1) / C, N, chains);
   dim3 block(C * F4<N>::N1);
-#define FZW_XY4(AX, NM) hipLaunchKernelGGL((xy4_pass_kernel<N, AX, NM>), grid, block, 0, s, a, tw)
-  if (axis == 0) FZW_XY4(0, 1);
-  else FZW_XY4(1, 1);
-#undef FZW_XY4
+  if (axis == 0) hipLaunchKernelGGL((xy4_pass_kernel<N, 0, 1>), grid, block, 0, s, a, tw);
+  else hipLaunchKernelGGL((xy4_pass_kernel<N, 1, 1>), grid, block, 0, s, a, tw);
 }
 
 template <int N>

@@ -306,7 +306,7 @@ struct Pass {
 thread_local fzw_plan* t_plan = nullptr;   // plan whose stages are being enqueued
 
 void run_pass(const Group& g, int axis, Pass& ps, int nmid, hipStream_t s) {
-  Timed tm(t_plan, axis == 0 ? FZW_K_XPASS : FZW_K_YPASS, (ps.a.nin + ps.a.nout) * spec_bytes(g));
+  Timed tm(t_plan, axis == 0 ? FZW_K_XMIX : FZW_K_YMIX, (ps.a.nin + ps.a.nout) * spec_bytes(g));
   ps.a.nmid = nmid;
   ps.a.chain_stride = g.ns;
   ps.a.tabs = g.tabs;
@@ -330,7 +330,7 @@ void pure_xy(const Group& g, int axis, bool inverse, float2* const* in, float2* 
     pa.chains = g.nc;
     pa.chain_stride = g.ns;
     if (has_pure_pass(g.n)) {
-      Timed tm(t_plan, axis == 0 ? FZW_K_XPASS : FZW_K_YPASS, 2.0 * k * spec_bytes(g));
+      Timed tm(t_plan, axis == 0 ? FZW_K_XPURE : FZW_K_YPURE, 2.0 * k * spec_bytes(g));
       if (launch_pure_pass(g.n, axis, inverse, pa, g.tw_full, s)) return;
     }
   }
@@ -419,7 +419,7 @@ bool lpt_z(fzw_plan* p, const Group& g, bool fwd, float2* const* in, float2* con
   a.d1 = (float)p->cosmo.d1;
   a.tau = (float)p->cosmo.tau_sc;
   if (!has_four_step_z(g.n)) return false;
-  Timed tm(p, FZW_K_LPT, (nin + nout) * spec_bytes(g) + 6 * field_bytes(g));
+  Timed tm(p, fwd ? FZW_K_LPT_FWD : FZW_K_LPT_BWD, (nin + nout) * spec_bytes(g) + 6 * field_bytes(g));
   return launch_lpt_z(g.n, fwd, a, g.nc, g.tw_half, g.tw_full, s);
 }
 
@@ -476,7 +476,7 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     la.tau = (float)p->cosmo.tau_sc;
     la.n = (long long)g.nc * g.nv;
     {
-      Timed tm(p, FZW_K_LPT, 8 * field_bytes(g));
+      Timed tm(p, FZW_K_LPT_FWD, 8 * field_bytes(g));
       launch_lpt_fwd(la, s);
     }
     float* src[2] = {g.s2, g.dsc};
@@ -525,7 +525,7 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     ca.sorted = g.sorted;
     ca.rho = g.rho;
     ca.acc = g.acc;
-    Timed tm(p, FZW_K_CIC, 4 * field_bytes(g));
+    Timed tm(p, FZW_K_CIC_DEP, 4 * field_bytes(g));
     if (p->cic_method == FZW_CIC_ATOMIC) launch_cic_deposit_atomic(ca, g.nc, s);
     else launch_cic_deposit(ca, g.nc, s);
   }
@@ -669,7 +669,7 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
     ca.n = g.n;
     ca.nv = g.nv;
     ca.drho = g.drho;
-    Timed tm(p, FZW_K_CIC, 7 * field_bytes(g));
+    Timed tm(p, FZW_K_CIC_ADJ, 7 * field_bytes(g));
     launch_cic_adjoint(ca, g.nc, s);
   }
   // ALPT adjoint: D = sum_j (-i k_j / k^2) rfft(dPsi_j)
@@ -712,7 +712,7 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
     la.tau = (float)p->cosmo.tau_sc;
     la.n = (long long)g.nc * g.nv;
     {
-      Timed tm(p, FZW_K_LPT, 14 * field_bytes(g));
+      Timed tm(p, FZW_K_LPT_BWD, 14 * field_bytes(g));
       launch_lpt_bwd(la, s);
     }
     zf(g, g.phi, &sp[5], 6, s);

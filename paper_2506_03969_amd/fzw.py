@@ -19,7 +19,10 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfzw.so"
 _lib = None
 
 WEB_PHI, WEB_DELTA = 0, 1
-KERNEL_CLASSES = ("z_r2c", "z_c2r", "y_pass", "x_pass", "cic", "lpt", "voxel_fwd", "likelihood", "voxel_bwd")
+KERNEL_CLASSES = ("z_r2c", "z_c2r", "y_mix", "x_mix", "y_pure", "x_pure", "lpt_fwd", "lpt_bwd", "cic_deposit",
+                  "cic_adjoint", "voxel_fwd", "likelihood", "voxel_bwd")
+# classes that are one kernel (template) each; the CIC deposit is a sequence
+SINGLE_KERNEL_CLASSES = tuple(c for c in KERNEL_CLASSES if c != "cic_deposit")
 
 
 class FzwError(RuntimeError):
