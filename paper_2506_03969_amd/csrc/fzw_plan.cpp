@@ -82,6 +82,9 @@ struct Group {
   int P = 0;                 // spectrum row pitch
   long long ns = 0;          // spectrum elements per chain
   int nblk = 0;              // blocks of the per-voxel kernels
+  double* partial = nullptr; // FP64 block partials of this group's reductions
+  hipStream_t gstream = nullptr;   // this group's stream when groups run side by side
+  hipEvent_t gdone = nullptr;
   float* tabs = nullptr;
   int tab_stride = 0;
   float2* tw_full = nullptr;
@@ -121,6 +124,7 @@ struct fzw_plan {
   hipStream_t user_stream = nullptr;  // the caller's stream
   hipStream_t cap_stream = nullptr;   // private stream for graph capture and replay
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipEvent_t ev_fork = nullptr;       // groups of different meshes fork from here
   double amp = 0;
   std::vector<Group> groups;
   std::vector<long long> chain_off;   // voxel offset per chain
@@ -182,8 +186,10 @@ T* dalloc(fzw_plan* p, size_t count) {
 struct Timed {
   fzw_plan* p;
   int idx = -1;
+  hipStream_t st = nullptr;
   Timed(fzw_plan* pl, int klass, double bytes) : p(pl) {
     if (!p || !p->timing) return;
+    st = p->stream;
     while (p->evpool.size() < p->evused + 2) {
       hipEvent_t e;
       HIPCHK(hipEventCreate(&e));
@@ -191,12 +197,12 @@ struct Timed {
     }
     fzw_plan::TimingRec r{klass, bytes, p->evpool[p->evused], p->evpool[p->evused + 1]};
     p->evused += 2;
-    HIPCHK(hipEventRecord(r.a, p->stream));
+    HIPCHK(hipEventRecord(r.a, st));
     p->recs.push_back(r);
     idx = (int)p->recs.size() - 1;
   }
   ~Timed() {
-    if (idx >= 0) (void)hipEventRecord(p->recs[idx].b, p->stream);
+    if (idx >= 0) (void)hipEventRecord(p->recs[idx].b, st);
   }
 };
 
@@ -557,7 +563,7 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     va.table = bias + (size_t)g.c0 * p->R * 4;
     va.logf = g.logf;
     va.beta = g.beta;
-    va.partial = p->partial;
+    va.partial = g.partial;
     va.x_floor = (float)p->cosmo.x_floor;
     va.steep = (float)p->web.steepness;
     va.lam_th = (float)p->web.lambda_th;
@@ -568,7 +574,7 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     }
     FinalArgs fa{};
     fa.mode = 0;
-    fa.partial = p->partial;
+    fa.partial = g.partial;
     fa.nblk = g.nblk;
     fa.scal = p->scal + (size_t)g.c0 * kScalStride;
     launch_finalize(fa, g.nc, s);
@@ -577,7 +583,7 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     la.beta = g.beta;
     la.counts = p->counts + p->chain_off[g.c0];
     la.scal = p->scal + (size_t)g.c0 * kScalStride;
-    la.partial = p->partial;
+    la.partial = g.partial;
     la.nbar = nbar ? nbar + p->chain_off[g.c0] : nullptr;
     if (grad) {
       la.ghat = g.ghat;
@@ -617,7 +623,7 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
     va.ghat = g.ghat;
     va.nbv = g.nbv;
     va.dbeta = g.dbeta;
-    va.partial = p->partial;
+    va.partial = g.partial;
     va.x_floor = (float)p->cosmo.x_floor;
     va.steep = (float)p->web.steepness;
     va.lam_th = (float)p->web.lambda_th;
@@ -628,7 +634,7 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
     }
     FinalArgs fa{};
     fa.mode = 2;
-    fa.partial = p->partial;
+    fa.partial = g.partial;
     fa.nblk = g.nblk;
     fa.scal = p->scal + (size_t)g.c0 * kScalStride;
     fa.dtable = dbias + (size_t)g.c0 * p->R * 4;
@@ -806,17 +812,44 @@ void check_ready(fzw_plan* p) {
     if (!p->counts_set[c]) throw Error(FZW_E_STATE, "counts of chain " + std::to_string(c) + " not set");
 }
 
+// Runs f(g) for every group.  Groups of different meshes share no buffer, so
+// with more than one they run side by side: each on its own stream, forked
+// from and joined back into the plan's stream with events (inside a stream
+// capture this becomes a fork / join of the graph).
+template <class F>
+void for_groups(fzw_plan* p, F&& f) {
+  if (p->groups.size() == 1) {
+    f(p->groups[0]);
+    return;
+  }
+  hipStream_t s0 = p->stream;
+  HIPCHK(hipEventRecord(p->ev_fork, s0));
+  for (auto& g : p->groups) {
+    HIPCHK(hipStreamWaitEvent(g.gstream, p->ev_fork, 0));
+    p->stream = g.gstream;
+    try {
+      f(g);
+    } catch (...) {
+      p->stream = s0;
+      throw;
+    }
+    p->stream = s0;
+    HIPCHK(hipEventRecord(g.gdone, g.gstream));
+  }
+  for (auto& g : p->groups) HIPCHK(hipStreamWaitEvent(s0, g.gdone, 0));
+}
+
 void forward_all(fzw_plan* p, const float* nu, const float* bias, float* nbar, double* logl) {
   t_plan = p;
-  for (auto& g : p->groups) forward_group(p, g, nu + p->chain_off[g.c0], bias, nbar, logl, false);
+  for_groups(p, [&](Group& g) { forward_group(p, g, nu + p->chain_off[g.c0], bias, nbar, logl, false); });
 }
 
 void value_and_grad_all(fzw_plan* p, const float* nu, const float* bias, double* logl, float* dnu, float* dbias) {
   t_plan = p;
-  for (auto& g : p->groups) {
+  for_groups(p, [&](Group& g) {
     forward_group(p, g, nu + p->chain_off[g.c0], bias, nullptr, logl, true);
     adjoint_group(p, g, bias, dnu + p->chain_off[g.c0], dbias);
-  }
+  });
 }
 
 template <class F>
@@ -843,6 +876,11 @@ void free_plan(fzw_plan* p) {
   }
   if (p->ev_in) (void)hipEventDestroy(p->ev_in);
   if (p->ev_out) (void)hipEventDestroy(p->ev_out);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  for (auto& g : p->groups) {
+    if (g.gdone) (void)hipEventDestroy(g.gdone);
+    if (g.gstream) (void)hipStreamDestroy(g.gstream);
+  }
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (void* a : p->allocs) (void)hipFree(a);
   for (auto e : p->evpool) (void)hipEventDestroy(e);
@@ -909,7 +947,12 @@ fzw_status fzw_plan_create(fzw_plan** out, int n_chains, const int* mesh_n, cons
       alloc_group(p, g);
       prime_launch_config(g.n);
       tune_fft(p, g);
-      part = std::max(part, (size_t)g.nc * g.nblk * (size_t)std::max(2, p->R * 4));
+      g.partial = dalloc<double>(p, std::max<size_t>((size_t)g.nc * g.nblk * (size_t)std::max(2, p->R * 4), 512));
+      if (p->groups.size() > 1) {
+        // default priority, non-blocking
+        HIPCHK(hipStreamCreateWithFlags(&g.gstream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&g.gdone, hipEventDisableTiming));
+      }
     }
     part = std::max<size_t>(part, 512);
     p->partial_elems = part;
@@ -929,6 +972,7 @@ fzw_status fzw_plan_create(fzw_plan** out, int n_chains, const int* mesh_n, cons
     HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
     HIPCHK(hipDeviceSynchronize());
   });
   if (st != FZW_OK) {
