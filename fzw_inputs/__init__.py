@@ -51,6 +51,9 @@ PRIOR_MU_BETA, PRIOR_SIGMA_BETA = 2.12, 0.20
 COL_ALPHA, COL_EPS, COL_RHO, COL_BETA = 0, 1, 2, 3
 
 
+RSD_RADIAL = 3   # rsd_axis value: radial RSD about an observer at the box centre
+
+
 @dataclass(frozen=True)
 class Cosmo:
     """Fixed cosmology and gravity-solver settings (held fixed, Section 2.1)."""
@@ -61,7 +64,7 @@ class Cosmo:
     d1: float = 1.0            # linear growth at the output redshift (z=0)
     f_growth: float = 0.31 ** 0.55  # linear growth rate used by RSD
     r_s: float = 4.0           # ALPT Gaussian smoothing radius
-    rsd_axis: int = -1         # -1: real space; 2: plane-parallel along z
+    rsd_axis: int = -1         # -1: real space; 0..2: plane-parallel along that axis; 3: radial (RSD_RADIAL)
     tau_sc: float = 0.05       # width of the smooth spherical-collapse hinge (0 = exact max)
     x_floor: float = 1e-6      # floor on 1+delta inside the bias
 

@@ -12,6 +12,8 @@ Plain NumPy/SciPy in float64, written stage by stage from the paper:
                 Section 2.8 fuzzy web, Section 2.6 bias, Section 2.7 likelihood)
                 and its hand-written adjoint
   hmc.py        potential, Hamiltonian and leapfrog (Sections 2.1-2.2)
+  nuts.py       the no-U-turn transition, dual averaging and Welford variances
+                used by the warm-up (Section 2.2, after the published method)
   stats.py      binned power-spectrum estimator (a test tool)
   mock.py       mock data from the forward model (Section 3 recipe)
 

@@ -20,7 +20,9 @@ Readings where the paper is silent or garbled (all listed in the design doc):
     curl free; optional smooth hinge of width tau_sc.
   * ALPT kernel K(k) = exp(-k^2 r_s^2 / 2) on the 2LPT part, 1-K on the SC part.
   * particles start on the mesh nodes, one per cell; CIC onto the same nodes.
-  * RSD: plane-parallel along z, s_z = x_z + f Psi_z.
+  * RSD: plane-parallel along z, s_z = x_z + f Psi_z; or radial about an
+    observer at the box centre, s = x + f (Psi.r) r / |r|^2 with r = x - centre
+    the particle's unwrapped Eulerian position, and no shift at r = 0.
   * Phi-web tensor k_i k_j W_G(kR)/k^2 delta_k; delta-web tensor
     ell^2 k_i k_j W_G(kR) delta_k ("parity unpinned": sign and scale reading).
   * eigenvalues sorted descending, memberships V,S,F,K = 1-w1, w1-w2, w2-w3, w3;
@@ -41,6 +43,7 @@ from scipy import special
 from . import cosmology
 
 PAIRS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
+RSD_RADIAL = 3          # rsd_axis value selecting radial RSD about the box centre
 WEB_PHI, WEB_DELTA = 0, 1
 _WORKERS = os.cpu_count() or 1
 
@@ -186,13 +189,31 @@ class Model:
         psi = np.stack([g.irfft(1j * g.k_odd[j] * g.inv_k2 * q_hat) for j in range(3)])
         return psi, dict(dl=dl, phi=phi, s2=s2, a=a, dsc=dsc)
 
+    def radial_frame(self, psi):
+        """Section 2.9 with the observer at the box centre (cell units): the
+        line-of-sight vector r from the observer to the real-space position,
+        |r|^2, the velocity displacement u = f Psi / dx (b_v = 1), and the
+        coefficient a = (u.r)/|r|^2 of the shift a r (0 where r = 0)."""
+        n, dx = self.s.n, self.g.dx
+        grid = np.indices((n, n, n), dtype=np.float64)
+        r = grid + psi / dx - 0.5 * n
+        r2 = np.sum(r * r, axis=0)
+        u = self.s.f_growth * psi / dx
+        safe = np.where(r2 > 0, r2, 1.0)
+        a = np.where(r2 > 0, np.sum(u * r, axis=0) / safe, 0.0)
+        return r, r2, u, a
+
     def positions(self, psi):
-        """Particle positions in cell units (lattice node + displacement), with
-        plane-parallel RSD along the configured axis (Section 2.9)."""
+        """Particle positions in cell units (lattice node + displacement), in
+        redshift space where RSD is on (Section 2.9): plane-parallel along the
+        configured axis, or radial about the box centre."""
         n, dx = self.s.n, self.g.dx
         grid = np.indices((n, n, n), dtype=np.float64)
         pos = grid + psi / dx
-        if self.s.rsd_axis >= 0:
+        if self.s.rsd_axis == RSD_RADIAL:
+            r, _, _, a = self.radial_frame(psi)
+            pos = pos + a * r
+        elif self.s.rsd_axis >= 0:
             ax = self.s.rsd_axis
             pos[ax] = pos[ax] + self.s.f_growth * psi[ax] / dx
         return pos
@@ -382,10 +403,18 @@ class Model:
             for (i, j), c in zip(PAIRS, comps):
                 ddelta_hat = ddelta_hat + g.hessian_factor(i, j) * m * g.rfft(c)
         ddelta = g.irfft(ddelta_hat) + dx_direct.reshape((s.n,) * 3)
-        # CIC adjoint, then RSD chain rule: s_ax = q_ax + (1+f) Psi_ax / dx
+        # CIC adjoint, then the RSD chain rule
         dpos = self.cic_adjoint(st["pos"], ddelta)
+        if s.rsd_axis == RSD_RADIAL:
+            # s = x + a r, with x = q + psi, r = x - centre, u = f psi and
+            # a = (u.r)/|r|^2: ds_i/dpsi_j = (1+a) delta_ij
+            #   + r_i (u_j + (f - 2a) r_j) / |r|^2, transposed onto dpos
+            r, r2, u, a = self.radial_frame(st["psi"])
+            gr = np.where(r2 > 0, np.sum(dpos * r, axis=0) / np.where(r2 > 0, r2, 1.0), 0.0)
+            dpos = (1.0 + a) * dpos + gr * (u + (s.f_growth - 2.0 * a) * r)
         dpsi = dpos / g.dx
-        if s.rsd_axis >= 0:
+        if 0 <= s.rsd_axis < 3:
+            # s_ax = q_ax + (1+f) Psi_ax / dx
             dpsi[s.rsd_axis] = dpsi[s.rsd_axis] * (1.0 + s.f_growth)
         # ALPT adjoint: conjugate multipliers
         dq_hat = 0.0

@@ -23,9 +23,11 @@ def oracle_model(w, chain=0):
 
 
 @functools.lru_cache(maxsize=16)
-def mock_case(name, n=None, tau_sc=None, chain=0):
+def mock_case(name, n=None, tau_sc=None, chain=0, rsd_axis=None):
     """(workload, oracle model, truth nu, eval nu, counts) for a workload."""
     kw = {"tau_sc": tau_sc} if tau_sc is not None else {}
+    if rsd_axis is not None:
+        kw["rsd_axis"] = rsd_axis
     w = workload_at(name, n, **kw)
     ch = w.chains[chain]
     m = oracle_model(w, chain)

@@ -8,10 +8,13 @@ from tests.torch_reference import value_and_grad_torch
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
 
-CASES = [("c0fd", None, 0.0), ("c2", 16, 0.0), ("c0fd", None, 0.05)]
+RADIAL = 3   # radial RSD about the box centre
+CASES = [("c0fd", None, 0.0, None), ("c2", 16, 0.0, None), ("c0fd", None, 0.05, None),
+         ("c2", 16, 0.0, RADIAL)]
 # finite-difference steps (truth point, evaluation point) per case, each inside
 # the range where the central difference has converged for these seeds
-STEPS = {("c0fd", 0.0): (1e-7, 1e-6), ("c2", 0.0): (1e-7, 1e-7), ("c0fd", 0.05): (1e-7, 1e-6)}
+STEPS = {("c0fd", 0.0, None): (1e-7, 1e-6), ("c2", 0.0, None): (1e-7, 1e-7),
+         ("c0fd", 0.05, None): (1e-7, 1e-6), ("c2", 0.0, RADIAL): (1e-7, 1e-7)}
 
 
 def _fd(m, nu, bias, counts, dnu=None, dbias=None, h=1e-7):
@@ -22,20 +25,20 @@ def _fd(m, nu, bias, counts, dnu=None, dbias=None, h=1e-7):
     return (m.forward(nu_p, b_p, counts)["logl"] - m.forward(nu_m, b_m, counts)["logl"]) / (2 * h)
 
 
-@pytest.mark.parametrize("name,n,tau", CASES)
+@pytest.mark.parametrize("name,n,tau,rsd", CASES)
 @pytest.mark.parametrize("which", ["truth", "eval"])
-def test_gradient_directional_fd(name, n, tau, which):
+def test_gradient_directional_fd(name, n, tau, rsd, which):
     """Central differences with a small step: the spherical-collapse hinge and
     the CIC cell faces make the map only piecewise smooth, so the step is kept
     well below the distance of the nearest kink in these fixed seeds."""
-    w, m, nu_t, nu_e, counts = mock_case(name, n, tau)
+    w, m, nu_t, nu_e, counts = mock_case(name, n, tau, rsd_axis=rsd)
     nu = nu_t if which == "truth" else nu_e
     bias = w.chains[0].bias
     logl, dnu, dbias = m.value_and_grad(nu, bias, counts)
     rng = np.random.default_rng(17)
     # the evaluation point has |logL| ~ 1e5 (tracers in empty cells), so its
     # step is larger to keep the round-off of the difference small
-    h = STEPS[(name, tau)][0 if which == "truth" else 1]
+    h = STEPS[(name, tau, rsd)][0 if which == "truth" else 1]
     for _ in range(3):
         v = rng.standard_normal(nu.shape)
         fd = _fd(m, nu, bias, counts, dnu=v, h=h)
@@ -43,10 +46,10 @@ def test_gradient_directional_fd(name, n, tau, which):
                                    abs=1e-7 * np.linalg.norm(dnu) + 50 * 1e-16 * abs(logl) / h)
 
 
-@pytest.mark.parametrize("name,n,tau", CASES[:2])
-def test_gradient_coordinates_fd(name, n, tau):
+@pytest.mark.parametrize("name,n,tau,rsd", CASES[:2] + CASES[3:])
+def test_gradient_coordinates_fd(name, n, tau, rsd):
     """64 random voxels of d logL / d nu, each by central differences."""
-    w, m, nu_t, nu_e, counts = mock_case(name, n, tau)
+    w, m, nu_t, nu_e, counts = mock_case(name, n, tau, rsd_axis=rsd)
     bias = w.chains[0].bias
     logl, dnu, _ = m.value_and_grad(nu_t, bias, counts)
     rng = np.random.default_rng(23)
@@ -59,9 +62,9 @@ def test_gradient_coordinates_fd(name, n, tau):
         assert fd == pytest.approx(dnu.ravel()[i], rel=1e-5, abs=1e-6 * scale + 50e-16 * abs(logl) / 1e-7)
 
 
-@pytest.mark.parametrize("name,n,tau", CASES[:2])
-def test_bias_table_gradient_fd(name, n, tau):
-    w, m, nu_t, nu_e, counts = mock_case(name, n, tau)
+@pytest.mark.parametrize("name,n,tau,rsd", CASES[:2] + CASES[3:])
+def test_bias_table_gradient_fd(name, n, tau, rsd):
+    w, m, nu_t, nu_e, counts = mock_case(name, n, tau, rsd_axis=rsd)
     bias = w.chains[0].bias
     logl, _, dbias = m.value_and_grad(nu_t, bias, counts)
     scale = np.abs(dbias).max()
@@ -73,11 +76,11 @@ def test_bias_table_gradient_fd(name, n, tau):
             assert fd == pytest.approx(dbias[r, c], rel=1e-5, abs=1e-7 * scale + 50e-16 * abs(logl) / 1e-5)
 
 
-@pytest.mark.parametrize("name,n,tau", CASES)
-def test_adjoint_matches_torch_autodiff(name, n, tau):
+@pytest.mark.parametrize("name,n,tau,rsd", CASES)
+def test_adjoint_matches_torch_autodiff(name, n, tau, rsd):
     """Element-wise agreement of logL, d/d nu and d/d bias with reverse-mode
     autodiff of an independent float64 PyTorch forward."""
-    w, m, nu_t, nu_e, counts = mock_case(name, n, tau)
+    w, m, nu_t, nu_e, counts = mock_case(name, n, tau, rsd_axis=rsd)
     bias = w.chains[0].bias
     for nu in (nu_t, nu_e):
         logl, dnu, dbias = m.value_and_grad(nu, bias, counts)

@@ -266,6 +266,37 @@ def test_rsd_plane_parallel_displaces_only_the_line_of_sight():
     assert np.allclose(pos[0] - grid[0], 0.25)
 
 
+def test_rsd_radial_moves_particles_along_the_observer_ray():
+    """Section 2.9 with the observer at the box centre and b_v = 1: each
+    particle stays on the ray from the observer through its real-space
+    position, its distance from the observer grows by the line-of-sight
+    component of f Psi, and on the line of sight through the centre along z
+    the shift equals the plane-parallel one."""
+    n, box = 8, 16.0
+    m = _model(n, box=box, rsd_axis=fi.RSD_RADIAL)
+    rng = np.random.default_rng(5)
+    psi = 0.6 * rng.standard_normal((3, n, n, n))
+    grid = np.indices((n, n, n), dtype=float)
+    x = grid + psi / m.g.dx - n / 2
+    s = m.positions(psi) - n / 2
+    xv, sv = x.reshape(3, -1).T, s.reshape(3, -1).T
+    assert np.allclose(np.cross(xv, sv), 0.0, atol=1e-12)
+    dist = np.linalg.norm(xv, axis=1)
+    vlos = np.einsum("pi,pi->p", m.s.f_growth * psi.reshape(3, -1).T / m.g.dx, xv) / dist
+    ahead = dist + vlos > 0
+    assert ahead.mean() > 0.9
+    assert np.allclose(np.linalg.norm(sv, axis=1)[ahead], (dist + vlos)[ahead], atol=1e-12)
+    # the line x = y = n/2 with Psi along z only: radial equals plane-parallel
+    pz = np.zeros((3, n, n, n))
+    pz[2] = psi[2]
+    mp = _model(n, box=box, rsd_axis=2)
+    c = n // 2
+    assert np.allclose(m.positions(pz)[:, c, c, :], mp.positions(pz)[:, c, c, :], atol=1e-12)
+    assert not np.allclose(m.positions(pz), mp.positions(pz))
+    # CIC keeps the mass
+    assert m.cic(m.positions(psi)).mean() == pytest.approx(1.0, abs=1e-13)
+
+
 # ---------------------------------------------------------------- web tensors
 def test_tidal_tensor_of_plane_wave_is_rank_one():
     """Phi-web with no smoothing: delta = A cos(k.x) has T = A cos(k.x) khat khat^T,

@@ -38,7 +38,15 @@ def logl_torch(m, nu, bias, counts):
     psi = [irf(1j * ko[j] * ik2 * q) for j in range(3)]
     grid = torch.as_tensor(np.indices((n, n, n), dtype=np.float64))
     pos = [grid[j] + psi[j] / g.dx for j in range(3)]
-    if s.rsd_axis >= 0:
+    if s.rsd_axis == 3:
+        # radial: move each particle along its ray from the box centre by the
+        # line-of-sight component of f Psi
+        ray = torch.stack(pos) - 0.5 * n
+        dist = torch.sqrt(torch.sum(ray * ray, dim=0))
+        rhat = ray / dist
+        vlos = torch.sum(s.f_growth * torch.stack(psi) / g.dx * rhat, dim=0)
+        pos = [pos[j] + vlos * rhat[j] for j in range(3)]
+    elif s.rsd_axis >= 0:
         pos[s.rsd_axis] = pos[s.rsd_axis] + s.f_growth * psi[s.rsd_axis] / g.dx
     p = torch.stack([c.reshape(-1) for c in pos])
     base = torch.floor(p.detach())
