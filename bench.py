@@ -31,6 +31,34 @@ KERNEL_SYMBOLS = {
     "likelihood": "fzw::likelihood_kernel", "voxel_bwd": "fzw::voxel_bwd_kernel<{w}>"}
 
 
+# sources whose kernels the stored byte counters describe
+TRAFFIC_SOURCES = ("paper_2506_03969_amd/csrc/fzw_fft.hip", "paper_2506_03969_amd/csrc/fzw_device.hpp",
+                   "paper_2506_03969_amd/csrc/fzw_internal.hpp")
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_class, n):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or
+    None when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%d.json" % (kernel_class, n))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_sha256") != sources_sha256():
+        return None
+    return float(d["hbm_bytes_per_launch"])
+
+
 def _plan(w, chains, Plan, CosmoParams, WebParams):
     c = w.cosmo
     cosmo = CosmoParams(c.omega_m, c.h, c.sigma8, c.n_s, c.d1, c.f_growth, c.r_s, c.rsd_axis, c.tau_sc,
@@ -128,6 +156,56 @@ def _trajectory(w, steps, reps, torch, Plan, CosmoParams, WebParams, step_size=1
     return ms
 
 
+def _nuts_leg(w, md, reps, torch, Plan, CosmoParams, WebParams, step_size=1e-5):
+    """Time no-U-turn transitions of every chain of workload w at a step so
+    small that no trajectory turns, so every transition builds the full tree
+    of 2^md - 1 leaves: the cost per leaf, next to a plain leapfrog step,
+    is the tree's bookkeeping overhead (checkpoints, U-turn dot products,
+    candidate copies, per-doubling host checks)."""
+    import numpy as np
+    import fzw_inputs as fi
+    from paper_2506_03969_amd import nuts_n_uniforms
+    plan = _plan(w, w.chains, Plan, CosmoParams, WebParams)
+    for c, ch in enumerate(w.chains):
+        plan.set_counts(c, torch.from_numpy(fi.timing_counts(ch).view(np.int16)).cuda())
+    mu, sig = fi.prior_arrays(w)
+    plan.set_sampling(fi.tie_array(w), mu, sig)
+    nu = torch.from_numpy(np.concatenate([fi.white_noise(ch, fi.ROLE_EVAL_NU).astype(np.float32).ravel()
+                                          for ch in w.chains])).cuda()
+    u = torch.from_numpy(np.stack([fi.free_start(w, ch) for ch in w.chains]).astype(np.float32)).cuda()
+    base = torch.from_numpy(np.stack([ch.bias for ch in w.chains]).astype(np.float32)).cuda()
+    minv = torch.ones_like(nu)
+    minv_u = torch.full_like(u, 1e-2)
+    step = torch.full((len(w.chains),), step_size, dtype=torch.float32, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    draws = []
+    for _ in range(reps + 1):
+        draws.append((torch.randn(nu.numel(), generator=gen, device="cuda"),
+                      torch.randn(tuple(u.shape), generator=gen, device="cuda"),
+                      torch.rand((len(w.chains), nuts_n_uniforms(md)), generator=gen, device="cuda")))
+    plan.nuts(nu, u, *draws[0][:2], base, minv, minv_u, step, draws[0][2], md)      # allocates the state
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    leaves = []
+    ev0.record(plan.stream)
+    for r in range(reps):
+        z, zu, uni = draws[r + 1]
+        pot, acc, st = plan.nuts(nu, u, z, zu, base, minv, minv_u, step, uni, md)
+        leaves.append(st[:, 1].clone())
+    ev1.record(plan.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    lv = torch.stack(leaves).float()
+    del plan
+    torch.cuda.empty_cache()
+    return {"chains": len(w.chains), "max_depth": md, "transitions": reps,
+            "leaves_per_transition": float(lv.mean()), "ms_per_transition": ms,
+            "ms_per_leaf": ms / float(lv.max(dim=1).values.mean()),
+            "chain_grads_per_s": float(lv.sum(dim=1).mean()) * 1e3 / ms}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +271,7 @@ def main():
     dom = max(((k, v) for k, v in rep.items() if k in SINGLE_KERNEL_CLASSES), key=lambda kv: kv[1][0])
     dom_ms, dom_n, dom_b = dom[1]
     achieved = dom_b / (dom_ms * 1e6)
+    traffic = measured_traffic(dom[0], n)
     total_alg = sum(v[2] for v in rep.values()) / args.steps
     for k, v in sorted(classes.items(), key=lambda kv: -kv[1]["ms_per_step"]):
         print("#   %-11s %7.3f ms/step %6.1f launches  %8.1f us/launch  %7.1f GB/s" % (
@@ -248,6 +327,18 @@ def main():
             print("# %s trajectory: %d chains, %.3f ms per leapfrog step (%.1f grads/s, %.0f GB/s model)" % (
                 name, len(wt.chains), ms, len(wt.chains) * 1e3 / ms, model / (ms * 1e6)), file=sys.stderr, flush=True)
 
+    # no-U-turn transitions of the 32 ragged chains (full trees of 31 leaves)
+    nuts_leg = None
+    if not args.no_trajectories:
+        wt = fi.workload("c3")
+        nuts_leg = _nuts_leg(wt, 5, 3, torch, Plan, CosmoParams, WebParams)
+        nuts_leg["workload"] = "c3: 32 chains (12 x 64^3, 10 x 96^3, 10 x 128^3)"
+        if trajectories and "c3" in trajectories:
+            nuts_leg["leaf_vs_leapfrog_step"] = nuts_leg["ms_per_leaf"] / trajectories["c3"]["ms_per_leapfrog_step"]
+        print("# c3 NUTS: %.2f ms per transition of %.0f leaves, %.3f ms per leaf (%.1f chain-grads/s)" % (
+            nuts_leg["ms_per_transition"], nuts_leg["leaves_per_transition"], nuts_leg["ms_per_leaf"],
+            nuts_leg["chain_grads_per_s"]), file=sys.stderr, flush=True)
+
     cpu = None if args.no_cpu else cpu_baseline(w)
     model_bytes = fi.bytes_model(n, w.web.n_webs)
     line = {
@@ -272,13 +363,15 @@ def main():
         "model_GBps": model_bytes / (ms_per_step * 1e6),
         "hbm_frac_model": model_bytes / (ms_per_step * 1e6) / HBM_PEAK_GBS,
         "trajectories": trajectories,
+        "nuts": nuts_leg,
         "algorithmic_GBps_all_kernels": total_alg / (ms_per_step * 1e6),
         "hbm_frac_algorithmic": total_alg / (ms_per_step * 1e6) / HBM_PEAK_GBS,
         "kernel_classes": classes,
         "fft_schedule": schedule,
         "roofline": {"bound": "hbm", "kernel": dom[0], "symbol": KERNEL_SYMBOLS.get(dom[0], "").format(n=n, w=w.web.n_webs),
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": dom_b / dom_n,
                      "avg_launch_us": 1e3 * dom_ms / dom_n},
         "cpu_baseline": cpu,
     }

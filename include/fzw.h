@@ -64,13 +64,21 @@ typedef enum {
 
 enum { FZW_WEB_PHI = 0, FZW_WEB_DELTA = 1 };
 
+/* rsd_axis value for radial redshift-space distortions (Section 2.9): each
+   particle moves along the ray from an observer at the box centre by the
+   line-of-sight component of f Psi, measured from its unwrapped real-space
+   position node + Psi; no shift where that position is the centre itself. */
+enum { FZW_RSD_RADIAL = 3 };
+
 /* Cosmology and gravity-solver settings, fixed for a plan (Section 2.1). */
 typedef struct {
   double omega_m, h, sigma8, n_s; /* BBKS linear spectrum normalised to sigma8 */
   double d1;                      /* linear growth factor at the output time */
   double f_growth;                /* growth rate used by the RSD shift */
   double r_s;                     /* ALPT Gaussian smoothing radius [Mpc/h] */
-  int rsd_axis;                   /* -1 real space; 0,1,2 plane-parallel line of sight */
+  int rsd_axis;                   /* -1 real space; 0,1,2 plane-parallel line of sight along
+                                     that axis; FZW_RSD_RADIAL radial about an observer at
+                                     the box centre (Section 2.9) */
   double tau_sc;                  /* width of a smooth spherical-collapse hinge, 0 = exact */
   double x_floor;                 /* floor applied to 1+delta inside the bias */
 } fzw_cosmo;
@@ -136,6 +144,65 @@ fzw_status fzw_set_sampling(fzw_plan* plan, const int* tie, int n_free, const do
 fzw_status fzw_leapfrog(fzw_plan* plan, float* nu, float* u, float* p_nu, float* p_u,
                         const float* bias_base, const float* minv_nu, const float* minv_u,
                         const float* step, int n_steps, double* h_start, double* h_end);
+
+/* One no-U-turn transition per chain (Section 2.2: the paper samples with
+ * NUTS; implemented after Hoffman & Gelman 2014 with multinomial selection and
+ * the generalised U-turn criterion of Betancourt 2017) on the potential of
+ * fzw_leapfrog.  The trajectory doubles in a drawn direction until the tree
+ * or a new subtree turns (a turning or diverging subtree, H - H0 > 1000, is
+ * discarded), or max_depth doublings are joined; the new state is drawn from
+ * the leaves with weights exp(-H) (uniformly within a subtree, with
+ * probability min(1, W_subtree / W_tree) when the subtree is joined).
+ * All chains advance in lock step; a chain whose trajectory has ended idles.
+ * All arrays are device memory:
+ *   nu, u              float32 state (packed chains; [n_chains][n_free]),
+ *                      replaced by the new state
+ *   z_nu, z_u          float32 standard normal draws, same layouts: the
+ *                      momentum is p = z / sqrt(minv)
+ *   bias_base, minv_nu, minv_u, step   as in fzw_leapfrog
+ *   uniforms           float32 [n_chains][2 max_depth + 2^max_depth - 1]
+ *                      draws in [0, 1): the direction of each doubling
+ *                      (>= 0.5 forward), the join of each doubling, then one
+ *                      per leaf in the order the leaves are made
+ *   max_depth          1 .. FZW_NUTS_MAX_DEPTH
+ *   potential          float64 [n_chains]: U at the new state
+ *   accept_stat        float64 [n_chains]: mean of min(1, exp(H0 - H)) over
+ *                      the leaves made (the statistic step-size adaptation
+ *                      uses)
+ *   stats              int32 [n_chains][3]: doublings joined, leapfrog steps
+ *                      taken, divergence flag
+ * The plan keeps (13 + 2 max_depth) float32 state vectors of the size of
+ * nu + u, allocated at the first call.  The caller's stream is synchronised
+ * once per doubling (the loop stops when every chain's trajectory has ended),
+ * so the call returns with the transition complete. */
+#define FZW_NUTS_MAX_DEPTH 12
+fzw_status fzw_nuts(fzw_plan* plan, float* nu, float* u, const float* z_nu, const float* z_u,
+                    const float* bias_base, const float* minv_nu, const float* minv_u, const float* step,
+                    const float* uniforms, int max_depth, double* potential, double* accept_stat,
+                    int* stats);
+
+/* Warm-up helpers for a diagonal mass matrix (device arrays of n floats, on
+ * the plan's stream).  fzw_welford adds sample number `count` (1-based) x to
+ * the running mean and sum of squared deviations m2 (Welford 1962; start from
+ * zeros).  fzw_inverse_mass writes the inverse mass from a window of count >= 2
+ * samples: (count/(count+5)) m2/(count-1) + 1e-3 * 5/(count+5), the
+ * regularised variance of Stan's windowed adaptation. */
+fzw_status fzw_welford(fzw_plan* plan, const float* x, float* mean, float* m2, long long n, int count);
+fzw_status fzw_inverse_mass(fzw_plan* plan, const float* m2, float* minv, long long n, int count);
+
+/* Step-size adaptation by dual averaging (Hoffman & Gelman 2014, Sec. 3.2),
+ * host only: init with the first step size and the target mean acceptance
+ * statistic (0.8 in common use), update after every warm-up transition with
+ * its accept_stat (returns the next step size), and take the averaged step
+ * from fzw_dual_avg_final after warm-up.  gamma 0.05, t0 10, kappa 0.75,
+ * mu = log(10 eps0). */
+typedef struct {
+  double mu, target, gamma, t0, kappa, h_bar, log_eps_bar;
+  long long t;
+} fzw_dual_avg;
+void fzw_dual_avg_init(fzw_dual_avg* state, double eps0, double target);
+double fzw_dual_avg_update(fzw_dual_avg* state, double accept_stat);
+double fzw_dual_avg_final(const fzw_dual_avg* state);
 
 /* Copy an intermediate field of the last forward evaluation (device
  * destination, float32 N^3 of one chain).  Fields: 0 delta_L, 1 Psi_x,

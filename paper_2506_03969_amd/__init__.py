@@ -1,8 +1,9 @@
 """MI355X (gfx950) implementation of the differentiable fuzzy-cosmic-web
-field-level likelihood: forward model, hand-written adjoint and leapfrog behind
+field-level likelihood: forward model, hand-written adjoint, leapfrog and NUTS behind
 the C ABI of include/fzw.h, with a thin PyTorch binding (fzw.py)."""
-from .fzw import (CosmoParams, FzwError, LogLikelihood, Plan, WebParams, WEB_DELTA, WEB_PHI, fft_schedule,
-                  load_library, set_fft_schedule)
+from .fzw import (CosmoParams, DualAveraging, FzwError, LogLikelihood, NUTS_MAX_DEPTH, Plan, RSD_RADIAL,
+                  WebParams, WEB_DELTA, WEB_PHI, fft_schedule, load_library, nuts_n_uniforms, set_fft_schedule)
 
-__all__ = ["CosmoParams", "FzwError", "LogLikelihood", "Plan", "WebParams", "WEB_DELTA", "WEB_PHI",
-           "fft_schedule", "load_library", "set_fft_schedule"]
+__all__ = ["CosmoParams", "DualAveraging", "FzwError", "LogLikelihood", "NUTS_MAX_DEPTH", "Plan", "RSD_RADIAL",
+           "WebParams", "WEB_DELTA", "WEB_PHI", "fft_schedule", "load_library", "nuts_n_uniforms",
+           "set_fft_schedule"]

@@ -83,8 +83,22 @@ __device__ __forceinline__ int wrap_index(int c, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Radial redshift-space geometry of one particle (Section 2.9, observer at
+// the box centre, cell units): r = node + d - n/2, the ray from the observer to
+// the real-space position, and a = f (d.r)/|r|^2, so that the redshift-space
+// position is node + d + a r (no shift at r = 0).
+struct RadialFrame {
+  float rx, ry, rz, r2, a;
+};
+
+// Locates a particle in the mesh: node index p, displacement d = psi * scale
+// (plus the radial shift when enabled), lower corner (cx, cy, cz) wrapped into
+// the box and fractional offsets (tx, ty, tz).  FRAME also returns the radial
+// frame and d before the shift, for the adjoint.
+template <bool FRAME = false>
 __device__ __forceinline__ void cic_locate(const CicArgs& a, int p, int n, int& cx, int& cy, int& cz,
-                                           float& tx, float& ty, float& tz) {
+                                           float& tx, float& ty, float& tz, RadialFrame* fr = nullptr,
+                                           float* d0 = nullptr) {
   const int q = (int)fast_div((unsigned)p, a.dn);
   const int iz = p - q * n;
   const int ix = (int)fast_div((unsigned)q, a.dn);
@@ -94,9 +108,27 @@ __device__ __forceinline__ void cic_locate(const CicArgs& a, int p, int n, int& 
     // per-kernel choice of the compiler, and every deposit and its adjoint
     // must see the same fractional offsets bit for bit
 #pragma clang fp contract(off)
-    const float dx = a.psi[0][p] * a.scale[0];
-    const float dy = a.psi[1][p] * a.scale[1];
-    const float dz = a.psi[2][p] * a.scale[2];
+    float dx = a.psi[0][p] * a.scale[0];
+    float dy = a.psi[1][p] * a.scale[1];
+    float dz = a.psi[2][p] * a.scale[2];
+    if (FRAME) {
+      d0[0] = dx;
+      d0[1] = dy;
+      d0[2] = dz;
+    }
+    if (a.radial) {
+      const int h = n >> 1;
+      const float rx = (float)(ix - h) + dx;
+      const float ry = (float)(iy - h) + dy;
+      const float rz = (float)(iz - h) + dz;
+      const float r2 = rx * rx + ry * ry + rz * rz;
+      const float ur = dx * rx + dy * ry + dz * rz;
+      const float s = r2 > 0.f ? a.f_los * ur / r2 : 0.f;
+      dx = dx + s * rx;
+      dy = dy + s * ry;
+      dz = dz + s * rz;
+      if (FRAME) *fr = RadialFrame{rx, ry, rz, r2, s};
+    }
     const float fx = floorf(dx), fy = floorf(dy), fz = floorf(dz);
     tx = dx - fx;
     ty = dy - fy;
@@ -363,7 +395,9 @@ __global__ void cic_adjoint_kernel(CicArgs a) {
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nv; p += (long long)gridDim.x * blockDim.x) {
     int cx, cy, cz;
     float tx, ty, tz;
-    cic_locate(b, (int)p, n, cx, cy, cz, tx, ty, tz);
+    RadialFrame fr;
+    float d0[3];
+    cic_locate<true>(b, (int)p, n, cx, cy, cz, tx, ty, tz, &fr, d0);
     const int nx = cx + 1 == n ? 0 : cx + 1;
     const int ny = cy + 1 == n ? 0 : cy + 1;
     const int nz = cz + 1 == n ? 0 : cz + 1;
@@ -377,6 +411,14 @@ __global__ void cic_adjoint_kernel(CicArgs a) {
       gx += v * sx * wy * wz;
       gy += v * wx * sy * wz;
       gz += v * wx * wy * sz;
+    }
+    if (a.radial) {
+      // transpose of ds_i/dd_j = (1+a) delta_ij + r_i (f d_j + (f - 2a) r_j) / |r|^2
+      const float gr = fr.r2 > 0.f ? (gx * fr.rx + gy * fr.ry + gz * fr.rz) / fr.r2 : 0.f;
+      const float f = a.f_los, cr = f - 2.f * fr.a, ca = 1.f + fr.a;
+      gx = ca * gx + gr * (f * d0[0] + cr * fr.rx);
+      gy = ca * gy + gr * (f * d0[1] + cr * fr.ry);
+      gz = ca * gz + gr * (f * d0[2] + cr * fr.rz);
     }
     a.dpsi[0][c * nv + p] = gx * a.scale[0];
     a.dpsi[1][c * nv + p] = gy * a.scale[1];
@@ -398,7 +440,9 @@ __global__ void cic_atomic_kernel(CicArgs a) {
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nv; p += (long long)gridDim.x * blockDim.x) {
     int cx, cy, cz;
     float tx, ty, tz;
-    cic_locate(b, (int)p, n, cx, cy, cz, tx, ty, tz);
+    RadialFrame fr;
+    float d0[3];
+    cic_locate<true>(b, (int)p, n, cx, cy, cz, tx, ty, tz, &fr, d0);
     const int nx = cx + 1 == n ? 0 : cx + 1;
     const int ny = cy + 1 == n ? 0 : cy + 1;
     const int nz = cz + 1 == n ? 0 : cz + 1;

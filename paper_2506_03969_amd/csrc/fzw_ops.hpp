@@ -39,7 +39,9 @@ __device__ __forceinline__ unsigned fast_div(unsigned x, const FastDiv& f) {
 
 struct CicArgs {
   const float* psi[3];
-  float scale[3];        // displacement -> cell units per axis (RSD factor included)
+  float scale[3];        // displacement -> cell units per axis (plane-parallel RSD factor included)
+  int radial;            // 1: radial RSD about the box centre (scale is then 1/dx on every axis)
+  float f_los;           // growth rate of the radial shift
   int n;
   FastDiv dn;            // division by n (set by the launchers)
   long long nv;
@@ -122,6 +124,85 @@ struct ParamArgs {
   const double* epartial;
   int ne, nfree;
 };
+
+// ---------------------------------------------------------------- NUTS
+// Per-chain scalar state of a no-U-turn transition (device).
+struct NutsChain {
+  double h0;        // Hamiltonian at the start
+  double log_w;     // log weight of the tree, relative to exp(-h0)
+  double log_ws;    // log weight of the subtree being built
+  double acc_sum;   // sum over leaves of min(1, exp(h0 - H))
+  double u_cand;    // potential at the tree's candidate
+  double u_sub;     // potential at the subtree's candidate
+  double u_leaf;    // potential at the last leaf
+  double prior;     // log-normal prior term of the free parameters at the last gradient
+  float eps;        // step size
+  float se;         // signed step of the current doubling (0: chain idle)
+  int v;            // direction of the current doubling
+  int active;       // the tree is still growing
+  int sub_active;   // the current subtree is still growing
+  int leaf_ok;      // the last leaf was made and did not diverge
+  int sel;          // the last leaf became the subtree's candidate
+  int merged;       // the last subtree was joined to the tree
+  int msel;         // and its candidate became the tree's
+  int diverging;
+  int depth;
+  int n_leaf;
+};
+
+// One piece of the NUTS state vectors: chains c0..c0+nc-1, each holding len
+// floats at off + (c - c0) * len; the field part (nu) or the free parameters.
+struct NutsSeg {
+  long long off, len;
+  int c0, nc;
+  int is_u;
+  const float* minv;   // inverse mass of chain c0's first coordinate
+  const float* z;      // momentum draws, same layout as minv
+};
+
+struct NutsVec {
+  float *wq, *wp, *wg;      // working leaf (g: d logL/d nu on the field, dU/du on the parameters)
+  float *lq, *lp, *lg;      // backward end of the tree
+  float *rq, *rp, *rg;      // forward end
+  float *cq, *sq;           // candidates of the tree and of the subtree
+  float *rho_t, *rho_s;     // momentum sums of the tree and of the subtree
+  float *ckp, *ckr;         // [max_depth][tv]: block-start momenta and prefix sums
+  long long tv;             // floats per state vector
+  NutsChain* st;
+  double* partial;          // [chains][kNutsBlk + 1][nval]
+  int nval;
+  int has_u;                // the parameter part exists (writes the last partial slot)
+};
+
+constexpr int kNutsBlk = 256;
+enum { kNutsOpKick = 0, kNutsOpDrift = 1, kNutsOpEnergy = 2, kNutsOpInit = 3, kNutsOpStart = 4, kNutsOpBegin = 5,
+       kNutsOpMerge = 6 };
+
+struct NutsLeafPlan {
+  int store;        // checkpoint slot written at this leaf, or -1
+  int nchk;         // aligned blocks that end at this leaf
+  int slot[12];     // their checkpoint slots (max_depth <= 12)
+};
+
+void launch_nuts_vec(const NutsVec& a, const NutsSeg& g, int op, hipStream_t s);
+void launch_nuts_leaf(const NutsVec& a, const NutsSeg& g, const NutsLeafPlan& lp, hipStream_t s);
+void launch_nuts_ugrad(const NutsVec& a, const ParamArgs& pa, long long uoff, int chains, hipStream_t s);
+struct NutsScalarArgs {
+  const float* step;        // [chains]
+  const float* uniforms;    // [chains][n_uniforms]
+  int n_uniforms, max_depth;
+  const double* scal;       // per-chain likelihood scalars (log-likelihood at kScalLogL)
+  int* any;                 // one flag: some chain (or subtree) still growing
+  double* potential;        // outputs
+  double* accept_stat;
+  int* stats;               // [chains][3]: depth, leapfrog steps, divergence
+};
+enum { kNutsInit = 0, kNutsBegin = 1, kNutsLeaf = 2, kNutsChecks = 3, kNutsJoin = 4, kNutsTree = 5, kNutsOut = 6,
+       kNutsAnyTree = 7, kNutsAnySub = 8 };
+void launch_nuts_scalar(const NutsVec& a, const NutsScalarArgs& sa, int chains, int mode, int j, int k, int nchk,
+                        hipStream_t s);
+void launch_welford(const float* x, float* mean, float* m2, long long n, int count, hipStream_t s);
+void launch_inv_mass(const float* m2, float* minv, long long n, int count, hipStream_t s);
 
 void launch_fill_i32(int* p, long long n, int v, hipStream_t s);
 void launch_fill_f32(float* p, long long n, float v, hipStream_t s);

@@ -161,6 +161,15 @@ struct fzw_plan {
     hipEvent_t a, b;
   };
   std::vector<TimingRec> recs;
+  // no-U-turn state, allocated at the first transition and grown with the
+  // tree depth or the number of free parameters
+  float* nuts_vec = nullptr;          // (13 + 2 max_depth) state vectors of nuts_tv floats
+  long long nuts_tv = 0;
+  int nuts_md = 0;
+  NutsChain* nuts_st = nullptr;
+  double* nuts_partial = nullptr;
+  int* nuts_any = nullptr;
+  int* nuts_any_host = nullptr;       // pinned
 };
 
 namespace {
@@ -208,6 +217,18 @@ struct Timed {
 
 double spec_bytes(const Group& g) { return (double)g.nc * g.n * g.n * (g.n / 2 + 1) * 8.0; }
 double field_bytes(const Group& g) { return (double)g.nc * g.nv * 4.0; }
+
+// Displacement-to-cell scaling and redshift-space geometry of the CIC stage
+// (Section 2.9, b_v = 1): plane-parallel RSD scales the line-of-sight axis by
+// 1 + f; radial RSD shifts along the ray from the box centre in the kernels.
+void set_rsd(CicArgs& ca, const fzw_cosmo& c, const Group& g) {
+  for (int d = 0; d < 3; ++d) {
+    const double f = (c.rsd_axis == d) ? (1.0 + c.f_growth) : 1.0;
+    ca.scale[d] = (float)(f * g.n / g.box);
+  }
+  ca.radial = c.rsd_axis == FZW_RSD_RADIAL ? 1 : 0;
+  ca.f_los = (float)c.f_growth;
+}
 
 bool supported_n(int n) {
   return n == 16 || n == 32 || n == 64 || n == 96 || n == 128 || n == 256 || n == 512;
@@ -453,20 +474,17 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     float* src[1] = {const_cast<float*>(nu)};
     zf(g, src, &sp[0], 1, s);
     pure_pass(g, Y, false, &sp[0], 1, s);
-    Pass ps;
-    ps.in(sp[0], true).out(sp[1], false);
-    ps.a.A[0][0] = spec(1.f, 0.f, NONE, NONE, TAB_H, NONE);
-    ps.a.B[0][0] = spec_const(1.f);
-    run_pass(g, X, ps, 1, s);
   }
-  // Section 2.3: Hessian of the first-order potential, phi_ij = k_i k_j / k^2 delta_L
+  // Section 2.3: Hessian of the first-order potential, phi_ij = k_i k_j / k^2
+  // delta_L, in the same x pass that forms delta_L (which stays in k space)
   {
     Pass ps;
-    ps.in(sp[1], false).out(sp[2], true).out(sp[3], true).out(sp[4], true);
-    ps.a.A[0][0] = spec_const(1.f);
-    ps.a.B[0][0] = spec(invn3, 0.f, X, X, TAB_INVK2, NONE);
-    ps.a.B[1][0] = spec(invn3, 0.f, X, NONE, TAB_INVK2, NONE);
-    ps.a.B[2][0] = spec(invn3, 0.f, NONE, NONE, TAB_INVK2, NONE);
+    ps.in(sp[0], true).out(sp[1], false).out(sp[2], true).out(sp[3], true).out(sp[4], true);
+    ps.a.A[0][0] = spec(1.f, 0.f, NONE, NONE, TAB_H, NONE);
+    ps.a.B[0][0] = spec_const(1.f);
+    ps.a.B[1][0] = spec(invn3, 0.f, X, X, TAB_INVK2, NONE);
+    ps.a.B[2][0] = spec(invn3, 0.f, X, NONE, TAB_INVK2, NONE);
+    ps.a.B[3][0] = spec(invn3, 0.f, NONE, NONE, TAB_INVK2, NONE);
     run_pass(g, X, ps, 1, s);
     hessian_yi(g, sp[2], sp[3], sp[4], &sp[5], s);
   }
@@ -515,14 +533,11 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     }
     zi(g, &sp[6], g.psi, 3, s);
   }
-  // CIC deposit (with plane-parallel RSD)
+  // CIC deposit (with plane-parallel or radial RSD, Section 2.9)
   {
     CicArgs ca{};
-    for (int d = 0; d < 3; ++d) {
-      ca.psi[d] = g.psi[d];
-      const double f = (p->cosmo.rsd_axis == d) ? (1.0 + p->cosmo.f_growth) : 1.0;
-      ca.scale[d] = (float)(f * g.n / g.box);
-    }
+    set_rsd(ca, p->cosmo, g);
+    for (int d = 0; d < 3; ++d) ca.psi[d] = g.psi[d];
     ca.n = g.n;
     ca.nv = g.nv;
     ca.count = g.count;
@@ -666,11 +681,10 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
   // CIC adjoint -> d Psi (in place over Psi)
   {
     CicArgs ca{};
+    set_rsd(ca, p->cosmo, g);
     for (int d = 0; d < 3; ++d) {
       ca.psi[d] = g.psi[d];
       ca.dpsi[d] = g.psi[d];
-      const double f = (p->cosmo.rsd_axis == d) ? (1.0 + p->cosmo.f_growth) : 1.0;
-      ca.scale[d] = (float)(f * g.n / g.box);
     }
     ca.n = g.n;
     ca.nv = g.nv;
@@ -883,8 +897,154 @@ void free_plan(fzw_plan* p) {
   }
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (void* a : p->allocs) (void)hipFree(a);
+  if (p->nuts_vec) (void)hipFree(p->nuts_vec);
+  if (p->nuts_st) (void)hipFree(p->nuts_st);
+  if (p->nuts_partial) (void)hipFree(p->nuts_partial);
+  if (p->nuts_any) (void)hipFree(p->nuts_any);
+  if (p->nuts_any_host) (void)hipHostFree(p->nuts_any_host);
   for (auto e : p->evpool) (void)hipEventDestroy(e);
   delete p;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ NUTS
+namespace {
+
+constexpr int kNutsVecs = 13;   // W(q,p,g), L(q,p,g), R(q,p,g), candidates (2), momentum sums (2)
+
+void nuts_reserve(fzw_plan* p, int md) {
+  const long long tv = p->total_vox + (long long)p->n_chains * p->nfree;
+  if (p->nuts_vec && p->nuts_tv == tv && p->nuts_md >= md) return;
+  HIPCHK(hipStreamSynchronize(p->stream));
+  if (p->nuts_vec) HIPCHK(hipFree(p->nuts_vec));
+  p->nuts_vec = nullptr;
+  const size_t n = (size_t)(kNutsVecs + 2 * md) * (size_t)tv;
+  if (hipMalloc(&p->nuts_vec, n * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    p->nuts_vec = nullptr;
+    throw Error(FZW_E_OOM, "hipMalloc of the NUTS state (" + std::to_string(n * 4) + " bytes) failed");
+  }
+  p->nuts_tv = tv;
+  p->nuts_md = md;
+  if (!p->nuts_st) {
+    const size_t pe = (size_t)p->n_chains * (kNutsBlk + 1) * (2 * 12);
+    HIPCHK(hipMalloc(&p->nuts_st, sizeof(NutsChain) * p->n_chains));
+    HIPCHK(hipMalloc(&p->nuts_partial, sizeof(double) * pe));
+    HIPCHK(hipMalloc(&p->nuts_any, sizeof(int)));
+    HIPCHK(hipHostMalloc(&p->nuts_any_host, sizeof(int), hipHostMallocDefault));
+  }
+}
+
+// Aligned blocks of the subtree that the leaf k closes (k odd) or opens (k even).
+NutsLeafPlan leaf_plan(int k) {
+  NutsLeafPlan lp{};
+  lp.store = -1;
+  if ((k & 1) == 0) {
+    lp.store = __builtin_popcount((unsigned)k);
+    return lp;
+  }
+  for (int m = 1; ((k + 1) & ((1 << m) - 1)) == 0 && lp.nchk < 12; ++m)
+    lp.slot[lp.nchk++] = __builtin_popcount((unsigned)(k + 1 - (1 << m)));
+  return lp;
+}
+
+bool nuts_any(fzw_plan* p, const NutsVec& a, NutsScalarArgs& sa, int mode) {
+  launch_nuts_scalar(a, sa, p->n_chains, mode, 0, 0, 0, p->stream);
+  HIPCHK(hipMemcpyAsync(p->nuts_any_host, sa.any, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return *p->nuts_any_host != 0;
+}
+
+void run_nuts(fzw_plan* p, float* nu, float* u, const float* z_nu, const float* z_u, const float* base,
+              const float* minv_nu, const float* minv_u, const float* step, const float* uniforms, int md,
+              double* potential, double* accept_stat, int* stats) {
+  nuts_reserve(p, md);
+  hipStream_t s = p->stream;
+  const int C = p->n_chains;
+  const long long tv = p->nuts_tv, tvox = p->total_vox;
+  float* v = p->nuts_vec;
+  NutsVec a{};
+  float** slots[kNutsVecs] = {&a.wq, &a.wp, &a.wg, &a.lq, &a.lp, &a.lg, &a.rq, &a.rp, &a.rg,
+                              &a.cq, &a.sq, &a.rho_t, &a.rho_s};
+  for (int i = 0; i < kNutsVecs; ++i) *slots[i] = v + (size_t)i * tv;
+  a.ckp = v + (size_t)kNutsVecs * tv;
+  a.ckr = a.ckp + (size_t)md * tv;
+  a.tv = tv;
+  a.st = p->nuts_st;
+  a.partial = p->nuts_partial;
+  a.nval = 2 * 12;
+  a.has_u = p->nfree > 0 ? 1 : 0;
+  std::vector<NutsSeg> segs;
+  for (auto& g : p->groups) {
+    const long long o = p->chain_off[g.c0];
+    segs.push_back(NutsSeg{o, g.nv, g.c0, g.nc, 0, minv_nu + o, z_nu + o});
+  }
+  if (p->nfree > 0) segs.push_back(NutsSeg{tvox, p->nfree, 0, C, 1, minv_u, z_u});
+  NutsScalarArgs sa{};
+  sa.step = step;
+  sa.uniforms = uniforms;
+  sa.max_depth = md;
+  sa.n_uniforms = 2 * md + (1 << md) - 1;
+  sa.scal = p->scal;
+  sa.any = p->nuts_any;
+  sa.potential = potential;
+  sa.accept_stat = accept_stat;
+  sa.stats = stats;
+  ParamArgs pa{};
+  pa.u = a.wq + tvox;
+  pa.mu = p->mu;
+  pa.sigma = p->sigma;
+  pa.tie = p->tie;
+  pa.base = base;
+  pa.table = p->table_tmp;
+  pa.dtable = p->dtable_tmp;
+  pa.ne = p->R * 4;
+  pa.nfree = p->nfree;
+  auto vec = [&](int op) {
+    for (auto& g : segs) launch_nuts_vec(a, g, op, s);
+  };
+  auto scalar = [&](int mode, int j, int k, int nchk) { launch_nuts_scalar(a, sa, C, mode, j, k, nchk, s); };
+  auto gradient = [&] {
+    launch_params(pa, C, 0, 0.f, kEBlk, nullptr, s);
+    value_and_grad_all(p, a.wq, p->table_tmp, nullptr, a.wg, p->dtable_tmp);
+    launch_nuts_ugrad(a, pa, tvox, C, s);
+  };
+  // start: gradient at the current state, momentum from the draws, H0
+  HIPCHK(hipMemcpyAsync(a.wq, nu, sizeof(float) * tvox, hipMemcpyDeviceToDevice, s));
+  if (p->nfree > 0)
+    HIPCHK(hipMemcpyAsync(a.wq + tvox, u, sizeof(float) * C * p->nfree, hipMemcpyDeviceToDevice, s));
+  gradient();
+  vec(kNutsOpInit);
+  vec(kNutsOpEnergy);
+  scalar(kNutsInit, 0, 0, 0);
+  vec(kNutsOpStart);
+  for (int j = 0; j < md; ++j) {
+    scalar(kNutsBegin, j, 0, 0);
+    vec(kNutsOpBegin);
+    const int nleaf = 1 << j;
+    for (int k = 0; k < nleaf; ++k) {
+      vec(kNutsOpKick);
+      vec(kNutsOpDrift);
+      gradient();
+      vec(kNutsOpKick);
+      vec(kNutsOpEnergy);
+      scalar(kNutsLeaf, j, k, 0);
+      const NutsLeafPlan lp = leaf_plan(k);
+      for (auto& g : segs) launch_nuts_leaf(a, g, lp, s);
+      if (lp.nchk > 0) scalar(kNutsChecks, j, k, lp.nchk);
+      // every chain's subtree may have ended early (turn or divergence)
+      if (k + 1 < nleaf && k >= 7 && ((k + 1) & k) == 0 && !nuts_any(p, a, sa, kNutsAnySub)) break;
+    }
+    scalar(kNutsJoin, j, 0, 0);
+    vec(kNutsOpMerge);
+    scalar(kNutsTree, j, 0, 0);
+    if (!nuts_any(p, a, sa, kNutsAnyTree)) break;
+  }
+  scalar(kNutsOut, 0, 0, 0);
+  HIPCHK(hipMemcpyAsync(nu, a.cq, sizeof(float) * tvox, hipMemcpyDeviceToDevice, s));
+  if (p->nfree > 0)
+    HIPCHK(hipMemcpyAsync(u, a.cq + tvox, sizeof(float) * C * p->nfree, hipMemcpyDeviceToDevice, s));
 }
 
 }  // namespace
@@ -904,7 +1064,8 @@ fzw_status fzw_plan_create(fzw_plan** out, int n_chains, const int* mesh_n, cons
   auto* p = new fzw_plan();
   fzw_status st = guarded([&] {
     if (web->n_webs < 1 || web->n_webs > 2) throw Error(FZW_E_ARG, "n_webs must be 1 or 2");
-    if (cosmo->rsd_axis < -1 || cosmo->rsd_axis > 2) throw Error(FZW_E_ARG, "rsd_axis must be -1..2");
+    if (cosmo->rsd_axis < -1 || cosmo->rsd_axis > FZW_RSD_RADIAL)
+      throw Error(FZW_E_ARG, "rsd_axis must be -1 (none), 0..2 (plane-parallel) or 3 (radial)");
     if (!(cosmo->x_floor > 0)) throw Error(FZW_E_ARG, "x_floor must be > 0");
     p->n_chains = n_chains;
     p->cosmo = *cosmo;
@@ -1157,6 +1318,67 @@ fzw_status fzw_leapfrog(fzw_plan* p, float* nu, float* u, float* p_nu, float* p_
     HIPCHK(hipStreamWaitEvent(p->user_stream, p->ev_out, 0));
   });
 }
+
+fzw_status fzw_nuts(fzw_plan* p, float* nu, float* u, const float* z_nu, const float* z_u, const float* bias_base,
+                    const float* minv_nu, const float* minv_u, const float* step, const float* uniforms,
+                    int max_depth, double* potential, double* accept_stat, int* stats) {
+  if (!p || !nu || !z_nu || !bias_base || !minv_nu || !step || !uniforms || !potential || !accept_stat || !stats ||
+      max_depth < 1 || max_depth > FZW_NUTS_MAX_DEPTH) {
+    g_last_error = "fzw_nuts: bad argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    check_ready(p);
+    if (p->nfree < 0) throw Error(FZW_E_STATE, "fzw_set_sampling not called");
+    if (p->nfree > 0 && (!u || !z_u || !minv_u)) throw Error(FZW_E_ARG, "u, z_u, minv_u required");
+    run_nuts(p, nu, u, z_nu, z_u, bias_base, minv_nu, minv_u, step, uniforms, max_depth, potential, accept_stat,
+             stats);
+  });
+}
+
+fzw_status fzw_welford(fzw_plan* p, const float* x, float* mean, float* m2, long long n, int count) {
+  if (!p || !x || !mean || !m2 || n < 0 || count < 1) {
+    g_last_error = "fzw_welford: bad argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    if (n > 0) launch_welford(x, mean, m2, n, count, p->stream);
+  });
+}
+
+fzw_status fzw_inverse_mass(fzw_plan* p, const float* m2, float* minv, long long n, int count) {
+  if (!p || !m2 || !minv || n < 0 || count < 2) {
+    g_last_error = "fzw_inverse_mass: bad argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    if (n > 0) launch_inv_mass(m2, minv, n, count, p->stream);
+  });
+}
+
+void fzw_dual_avg_init(fzw_dual_avg* s, double eps0, double target) {
+  s->mu = std::log(10.0 * eps0);
+  s->target = target;
+  s->gamma = 0.05;
+  s->t0 = 10.0;
+  s->kappa = 0.75;
+  s->t = 0;
+  s->h_bar = 0.0;
+  s->log_eps_bar = 0.0;
+}
+
+double fzw_dual_avg_update(fzw_dual_avg* s, double accept_stat) {
+  s->t += 1;
+  const double t = (double)s->t;
+  const double w = 1.0 / (t + s->t0);
+  s->h_bar = (1.0 - w) * s->h_bar + w * (s->target - accept_stat);
+  const double log_eps = s->mu - std::sqrt(t) / s->gamma * s->h_bar;
+  const double eta = std::pow(t, -s->kappa);
+  s->log_eps_bar = eta * log_eps + (1.0 - eta) * s->log_eps_bar;
+  return std::exp(log_eps);
+}
+
+double fzw_dual_avg_final(const fzw_dual_avg* s) { return std::exp(s->log_eps_bar); }
 
 fzw_status fzw_get_field(fzw_plan* p, int chain, int field, float* out) {
   if (!p || !out || chain < 0 || chain >= p->n_chains || field < 0 || field >= 6 + 6 * p->W) {

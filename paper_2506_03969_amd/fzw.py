@@ -19,6 +19,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfzw.so"
 _lib = None
 
 WEB_PHI, WEB_DELTA = 0, 1
+RSD_RADIAL = 3          # rsd_axis value: radial RSD about an observer at the box centre
 KERNEL_CLASSES = ("z_r2c", "z_c2r", "y_mix", "x_mix", "y_pure", "x_pure", "lpt_fwd", "lpt_bwd", "cic_deposit",
                   "cic_adjoint", "voxel_fwd", "likelihood", "voxel_bwd")
 # classes that are one kernel (template) each; the CIC deposit is a sequence
@@ -39,6 +40,20 @@ class CCosmo(ctypes.Structure):
 class CWeb(ctypes.Structure):
     _fields_ = [("n_webs", ctypes.c_int), ("kind", ctypes.c_int * 2), ("smooth_r", ctypes.c_double * 2),
                 ("ell", ctypes.c_double * 2), ("steepness", ctypes.c_double), ("lambda_th", ctypes.c_double)]
+
+
+class CDualAvg(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("target", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("t0", ctypes.c_double), ("kappa", ctypes.c_double), ("h_bar", ctypes.c_double),
+                ("log_eps_bar", ctypes.c_double), ("t", ctypes.c_longlong)]
+
+
+NUTS_MAX_DEPTH = 12
+
+
+def nuts_n_uniforms(max_depth: int) -> int:
+    """Uniform draws one NUTS transition consumes per chain."""
+    return 2 * max_depth + (1 << max_depth) - 1
 
 
 def load_library(path: str = _LIB_PATH):
@@ -78,8 +93,19 @@ def load_library(path: str = _LIB_PATH):
     lib.fzw_workspace_bytes.argtypes = [vp]
     lib.fzw_workspace_bytes.restype = sz
     lib.fzw_last_error.restype = ctypes.c_char_p
+    lib.fzw_nuts.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i, vp, vp, vp]
+    ll = ctypes.c_longlong
+    lib.fzw_welford.argtypes = [vp, vp, vp, vp, ll, i]
+    lib.fzw_inverse_mass.argtypes = [vp, vp, vp, ll, i]
+    lib.fzw_dual_avg_init.argtypes = [ctypes.POINTER(CDualAvg), d, d]
+    lib.fzw_dual_avg_init.restype = None
+    lib.fzw_dual_avg_update.argtypes = [ctypes.POINTER(CDualAvg), d]
+    lib.fzw_dual_avg_update.restype = d
+    lib.fzw_dual_avg_final.argtypes = [ctypes.POINTER(CDualAvg)]
+    lib.fzw_dual_avg_final.restype = d
     for name in ("fzw_plan_create", "fzw_set_counts", "fzw_forward", "fzw_value_and_grad",
-                 "fzw_set_sampling", "fzw_leapfrog", "fzw_get_field", "fzw_fft_r2c", "fzw_fft_c2r"):
+                 "fzw_set_sampling", "fzw_leapfrog", "fzw_get_field", "fzw_fft_r2c", "fzw_fft_c2r",
+                 "fzw_nuts", "fzw_welford", "fzw_inverse_mass"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -225,6 +251,30 @@ class Plan:
                                  _ptr(h_end, torch.float64)), "fzw_leapfrog")
         return h_start, h_end
 
+    def nuts(self, nu, u, z_nu, z_u, bias_base, minv_nu, minv_u, step, uniforms, max_depth):
+        """One no-U-turn transition per chain (fzw_nuts); nu and u are replaced
+        by the new state.  Returns (potential, accept_stat, stats[chains][3])."""
+        pot = torch.empty(self.n_chains, dtype=torch.float64, device=self.device)
+        acc = torch.empty(self.n_chains, dtype=torch.float64, device=self.device)
+        stats = torch.empty((self.n_chains, 3), dtype=torch.int32, device=self.device)
+        if uniforms.shape[-1] != nuts_n_uniforms(max_depth) or not uniforms.is_contiguous():
+            raise FzwError("uniforms must be contiguous [chains][%d]" % nuts_n_uniforms(max_depth))
+        _check(_lib.fzw_nuts(self._h, _ptr(nu, torch.float32), _ptr(u), _ptr(z_nu, torch.float32), _ptr(z_u),
+                             _ptr(bias_base, torch.float32), _ptr(minv_nu, torch.float32), _ptr(minv_u),
+                             _ptr(step, torch.float32), _ptr(uniforms, torch.float32), int(max_depth),
+                             _ptr(pot, torch.float64), _ptr(acc, torch.float64), _ptr(stats, torch.int32)),
+               "fzw_nuts")
+        return pot, acc, stats
+
+    def welford(self, x, mean, m2, count):
+        """Adds sample `count` (1-based) x to the running mean and m2."""
+        _check(_lib.fzw_welford(self._h, _ptr(x, torch.float32), _ptr(mean, torch.float32), _ptr(m2, torch.float32),
+                                x.numel(), int(count)), "fzw_welford")
+
+    def inverse_mass(self, m2, minv, count):
+        _check(_lib.fzw_inverse_mass(self._h, _ptr(m2, torch.float32), _ptr(minv, torch.float32), m2.numel(),
+                                     int(count)), "fzw_inverse_mass")
+
     def set_cic_method(self, method: str):
         """'sorted' (counting sort + gather, default) or 'atomic' (fixed-point
         integer atomics); both give bit-identical densities."""
@@ -266,6 +316,21 @@ class Plan:
 
 
 FFT_FAMILIES = ("four-step", "stockham")
+
+
+class DualAveraging:
+    """Step-size adaptation by dual averaging (fzw_dual_avg_*), one per chain."""
+
+    def __init__(self, eps0: float, target: float = 0.8):
+        load_library()
+        self._s = CDualAvg()
+        _lib.fzw_dual_avg_init(ctypes.byref(self._s), float(eps0), float(target))
+
+    def update(self, accept_stat: float) -> float:
+        return _lib.fzw_dual_avg_update(ctypes.byref(self._s), float(accept_stat))
+
+    def final(self) -> float:
+        return _lib.fzw_dual_avg_final(ctypes.byref(self._s))
 
 
 def fft_schedule(mesh_n: int):

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -69,3 +70,17 @@ def test_fft_schedule_query_and_validation_without_gpu(lib):
     assert lib.fzw_set_fft_schedule(16, 1, 1, 0) == 0
     assert lib.fzw_fft_schedule(16, ctypes.byref(z), ctypes.byref(xy), ctypes.byref(pure), None) == 0
     assert (z.value, xy.value, pure.value) == (1, 1, 0)
+
+
+def test_dual_averaging_host_functions_match_the_oracle():
+    """The library's host-side step-size adaptation follows the same
+    recursion as the oracle's, to rounding."""
+    import math
+    from oracle import nuts
+    from paper_2506_03969_amd import DualAveraging
+    ours, ref = DualAveraging(0.3, 0.8), nuts.DualAveraging(0.3, 0.8)
+    rng = np.random.default_rng(4)
+    for a in rng.uniform(0.2, 1.0, size=200):
+        assert ours.update(a) == pytest.approx(ref.update(a), rel=1e-12)
+    assert ours.final() == pytest.approx(ref.final(), rel=1e-12)
+    assert math.isfinite(ours.final())

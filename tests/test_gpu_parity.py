@@ -55,8 +55,8 @@ def test_fft_matches_numpy(fft_plans, n):
     assert err2 < 2e-6
 
 
-def _state(name, n, which, tau_sc=None):
-    w, m, nu_t, nu_e, counts = mock_case(name, n, tau_sc)
+def _state(name, n, which, tau_sc=None, rsd=None):
+    w, m, nu_t, nu_e, counts = mock_case(name, n, tau_sc, rsd_axis=rsd)
     if which == "truth":
         nu = nu_t
     elif which == "near":
@@ -66,8 +66,8 @@ def _state(name, n, which, tau_sc=None):
     return w, m, nu, counts
 
 
-def _gpu_forward(name, n, which="truth", tau_sc=None):
-    w, m, nu, counts = _state(name, n, which, tau_sc)
+def _gpu_forward(name, n, which="truth", tau_sc=None, rsd=None):
+    w, m, nu, counts = _state(name, n, which, tau_sc, rsd)
     ch = w.chains[0]
     p = plan_for(w)
     p.set_counts(0, dev_counts(counts))
@@ -75,11 +75,16 @@ def _gpu_forward(name, n, which="truth", tau_sc=None):
     return w, m, nu, counts, p, bias
 
 
-@pytest.mark.parametrize("case", CASES, ids=_ids)
+RADIAL = 3   # radial RSD about the box centre
+RADIAL_CASES = [("c0fd", None), ("c2", 32), ("c2", 64), ("c2", 96)]
+
+
+@pytest.mark.parametrize("case,rsd", [(c, None) for c in CASES] + [(c, RADIAL) for c in RADIAL_CASES],
+                         ids=lambda x: _ids(x) if isinstance(x, tuple) else ("radial" if x == RADIAL else "los"))
 @pytest.mark.parametrize("which", ["truth", "near", "eval"])
-def test_forward_stages_and_logl(case, which):
+def test_forward_stages_and_logl(case, rsd, which):
     name, n = case
-    w, m, nu, counts, p, bias = _gpu_forward(name, n, which)
+    w, m, nu, counts, p, bias = _gpu_forward(name, n, which, rsd=rsd)
     logl, nbar = p.forward(dev(nu.ravel()), bias, want_nbar=True)
     st = m.forward(nu, w.chains[0].bias, counts)
     errs = {
@@ -102,13 +107,15 @@ def test_forward_stages_and_logl(case, which):
         assert v < tol, (k, v)
 
 
-GRAD_CASES = ([(c, "truth", None) for c in CASES] + [(c, "near", None) for c in CASES]
-              + [(c, "truth", 0.0) for c in CASES[1:]] + [(c, "eval", None) for c in CASES[1:]])
+GRAD_CASES = ([(c, "truth", None, None) for c in CASES] + [(c, "near", None, None) for c in CASES]
+              + [(c, "truth", 0.0, None) for c in CASES[1:]] + [(c, "eval", None, None) for c in CASES[1:]]
+              + [(c, which, None, RADIAL) for c in RADIAL_CASES for which in ("truth", "near")])
 
 
 def _gid(x):
-    (name, n), which, tau = x
-    return "%s-%s-%s%s" % (name, n, which, "-exact_hinge" if tau == 0.0 else "")
+    (name, n), which, tau, rsd = x
+    return "%s-%s-%s%s%s" % (name, n, which, "-exact_hinge" if tau == 0.0 else "",
+                             "-radial" if rsd == RADIAL else "")
 
 
 @pytest.mark.parametrize("gcase", GRAD_CASES, ids=_gid)
@@ -120,8 +127,8 @@ def test_gradient(gcase):
     diverges at delta_L = 3/2), at a white-noise state drawn independently of
     the data (tracers in nearly empty cells, gradient ~ 1/x^2), and for bias
     entries at the data's own parameters (their voxel sums cancel to ~1%)."""
-    (name, n), which, tau = gcase
-    w, m, nu, counts, p, bias = _gpu_forward(name, n, which, tau)
+    (name, n), which, tau, rsd = gcase
+    w, m, nu, counts, p, bias = _gpu_forward(name, n, which, tau, rsd)
     logl, dnu, dbias = p.value_and_grad(dev(nu.ravel()), bias)
     ref_l, ref_dnu, ref_db = m.value_and_grad(nu, w.chains[0].bias, counts)
     e_l = abs(float(host(logl)[0]) - ref_l) / abs(ref_l)
@@ -193,10 +200,11 @@ def test_rejects_unsupported_mesh():
         plan_for(w)
 
 
-def test_cic_methods_bit_identical():
+@pytest.mark.parametrize("rsd", [None, RADIAL], ids=["los", "radial"])
+def test_cic_methods_bit_identical(rsd):
     """The sorted-gather deposit and the fixed-point atomic deposit give the
     same density bit for bit (same FP32 weights, exact integer sums)."""
-    w, m, nu, counts, p, bias = _gpu_forward("c2", 64, "near")
+    w, m, nu, counts, p, bias = _gpu_forward("c2", 64, "near", rsd=rsd)
     x = dev(nu.ravel())
     l1 = p.forward(x, bias).clone()
     r1 = p.get_field(0, 4).clone()
