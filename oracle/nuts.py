@@ -54,8 +54,14 @@ def _logaddexp(a: float, b: float) -> float:
     return m + math.log(math.exp(a - m) + math.exp(b - m))
 
 
-def _turning(minv, p_minus, p_plus, rho) -> bool:
-    return float(np.dot(minv * p_minus, rho)) <= 0.0 or float(np.dot(minv * p_plus, rho)) <= 0.0
+def _turning(minv, p_minus, p_plus, rho, margins=None) -> bool:
+    a = float(np.dot(minv * p_minus, rho))
+    b = float(np.dot(minv * p_plus, rho))
+    if margins is not None:
+        nr = np.linalg.norm(rho)
+        margins.append(min(abs(a) / (np.linalg.norm(minv * p_minus) * nr + 1e-300),
+                           abs(b) / (np.linalg.norm(minv * p_plus) * nr + 1e-300)))
+    return a <= 0.0 or b <= 0.0
 
 
 @dataclass
@@ -68,6 +74,12 @@ class Transition:
     n_leapfrog: int        # leaves made (leapfrog steps taken)
     diverging: bool
     h0: float
+    # smallest distance of any random or sign decision from its threshold:
+    # |uniform - probability| for candidate choices and joins, and
+    # |(M^-1 p) . rho| / (|M^-1 p| |rho|) for U-turn checks (how far a result
+    # computed with a different rounding can move before a decision flips)
+    margin_choice: float = math.inf
+    margin_turn: float = math.inf
 
 
 def transition(pot_grad, q0, z, minv, eps, uniforms, max_depth, start=None):
@@ -84,6 +96,7 @@ def transition(pot_grad, q0, z, minv, eps, uniforms, max_depth, start=None):
     log_w = 0.0                      # log of the tree's weight, relative to exp(-H0)
     rho = p0.copy()
     acc_sum, n_leaf, depth, diverging = 0.0, 0, 0, False
+    m_choice, m_turn = [math.inf], [math.inf]
     for j in range(max_depth):
         v = 1 if uniforms[j] >= 0.5 else -1
         q, p, g = ends[v]
@@ -102,14 +115,17 @@ def transition(pot_grad, q0, z, minv, eps, uniforms, max_depth, start=None):
                 diverging = stop = True
                 break
             log_ws = _logaddexp(log_ws, h0 - h)
-            if uniforms[2 * max_depth + (1 << j) - 1 + k] < math.exp((h0 - h) - log_ws):
+            r, prob = uniforms[2 * max_depth + (1 << j) - 1 + k], math.exp((h0 - h) - log_ws)
+            if k > 0:
+                m_choice.append(abs(r - prob))
+            if r < prob:
                 cand_s = (q, g, u_pot)
             leaves_p.append(p)
             # every aligned block of 2, 4, ... leaves that ends here
             size = 2
             while (k + 1) % size == 0:
                 blk = leaves_p[k + 1 - size:k + 1]
-                if _turning(minv, blk[0], blk[-1], np.sum(blk, axis=0)):
+                if _turning(minv, blk[0], blk[-1], np.sum(blk, axis=0), m_turn):
                     stop = True
                     break
                 size *= 2
@@ -117,15 +133,19 @@ def transition(pot_grad, q0, z, minv, eps, uniforms, max_depth, start=None):
                 break
         if stop:
             break
-        if uniforms[max_depth + j] < math.exp(min(0.0, log_ws - log_w)):
+        r, prob = uniforms[max_depth + j], math.exp(min(0.0, log_ws - log_w))
+        if prob < 1.0:
+            m_choice.append(abs(r - prob))
+        if r < prob:
             cand = cand_s
         log_w = _logaddexp(log_w, log_ws)
         ends[v] = (q, p, g)
         rho = rho + np.sum(leaves_p, axis=0)
         depth = j + 1
-        if _turning(minv, ends[-1][1], ends[+1][1], rho):
+        if _turning(minv, ends[-1][1], ends[+1][1], rho, m_turn):
             break
-    return Transition(cand[0], cand[1], cand[2], acc_sum / max(n_leaf, 1), depth, n_leaf, diverging, h0)
+    return Transition(cand[0], cand[1], cand[2], acc_sum / max(n_leaf, 1), depth, n_leaf, diverging, h0,
+                      min(m_choice), min(m_turn))
 
 
 class DualAveraging:
