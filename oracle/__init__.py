@@ -14,6 +14,7 @@ Plain NumPy/SciPy in float64, written stage by stage from the paper:
   hmc.py        potential, Hamiltonian and leapfrog (Sections 2.1-2.2)
   nuts.py       the no-U-turn transition, dual averaging and Welford variances
                 used by the warm-up (Section 2.2, after the published method)
+  wiener.py     the Wiener-filter starting point of the chains (Section 2.2)
   stats.py      binned power-spectrum estimator (a test tool)
   mock.py       mock data from the forward model (Section 3 recipe)
 

@@ -460,3 +460,30 @@ def test_equal_regions_make_the_web_irrelevant():
     assert np.allclose(st["nbar"], want, rtol=1e-10, atol=1e-300)
     ref = stats.nbinom.logpmf(c.ravel(), 4.0, 4.0 / (4.0 + want))
     assert st["logl"] == pytest.approx(ref.sum(), rel=1e-10)
+
+
+# ---------------------------------------------------------------- Wiener start
+def test_wiener_start_is_the_gaussian_posterior_mean():
+    """Section 2.2 initialisation: on a 4^3 mesh, the oracle's Fourier-diagonal
+    Wiener filter equals the textbook posterior mean of nu under nu ~ N(0, I),
+    delta_tr = L nu + shot noise of variance 1/nbar per cell, written with
+    dense matrices: E[nu | d] = L^T (L L^T + I/nbar)^-1 d, where L is the
+    linear-density operator built column by column from the model."""
+    from oracle import wiener
+    n = 4
+    m = _model(n, box=40.0)
+    rng = np.random.default_rng(8)
+    counts = rng.poisson(1.5, size=(n, n, n))
+    dim = n ** 3
+    cols = []
+    for i in range(dim):
+        e = np.zeros(dim)
+        e[i] = 1.0
+        cols.append(m.g.irfft(m.linear_density_hat(e.reshape(n, n, n))).ravel())
+    L = np.stack(cols, axis=1)
+    nbar = counts.sum() / dim
+    d = wiener.tracer_contrast(counts).ravel()
+    want = L.T @ np.linalg.solve(L @ L.T + np.eye(dim) / nbar, d)
+    got = wiener.wiener_white_noise(m, counts).ravel()
+    assert np.allclose(got, want, rtol=1e-9, atol=1e-12 * np.abs(want).max())
+    assert abs(wiener.tracer_contrast(counts).mean()) < 1e-14
