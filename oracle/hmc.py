@@ -61,3 +61,44 @@ def leapfrog(grad_fn, q_nu, q_u, p_nu, p_u, minv_nu, minv_u, eps, n_steps):
         p_u -= 0.5 * eps * g_u
     h1 = pot + kinetic(p_nu, p_u, minv_nu, minv_u)
     return q_nu, q_u, p_nu, p_u, h0, h1
+
+
+# Splitting integrators (Section 2.2 names second- and fourth-order HMC and
+# the variant of Blanes, Casas & Sanz-Serna 2014).  One step is
+#   K(a_0) D(b_1) K(a_1) ... D(b_m) K(a_m)
+# with K(a) the kick p -= a eps dU/dq and D(b) the drift q += b eps M^-1 p,
+# and the gradient evaluated after every drift.
+_W1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+_W0 = -(2.0 ** (1.0 / 3.0)) * _W1
+_B2 = 0.21178
+SCHEMES = {
+    # kick-drift-kick (second order, one gradient per step)
+    "leapfrog": ((0.5, 0.5), (1.0,)),
+    # two-stage splitting with b = 0.21178, minimising the energy error of
+    # Gaussian targets (Blanes, Casas & Sanz-Serna 2014; two gradients)
+    "blanes2": ((_B2, 1.0 - 2.0 * _B2, _B2), (0.5, 0.5)),
+    # fourth order: three leapfrog steps of w1, w0, w1 (Yoshida 1990;
+    # Forest & Ruth 1990), adjacent kicks merged (three gradients)
+    "yoshida4": ((0.5 * _W1, 0.5 * (_W1 + _W0), 0.5 * (_W0 + _W1), 0.5 * _W1), (_W1, _W0, _W1)),
+}
+
+
+def integrate(grad_fn, q_nu, q_u, p_nu, p_u, minv_nu, minv_u, eps, n_steps, scheme="leapfrog"):
+    """n_steps of a splitting scheme from SCHEMES; same arguments and returns
+    as `leapfrog`."""
+    kicks, drifts = SCHEMES[scheme]
+    q_nu, q_u = np.array(q_nu, dtype=np.float64), np.array(q_u, dtype=np.float64)
+    p_nu, p_u = np.array(p_nu, dtype=np.float64), np.array(p_u, dtype=np.float64)
+    pot, g_nu, g_u = grad_fn(q_nu, q_u)
+    h0 = pot + kinetic(p_nu, p_u, minv_nu, minv_u)
+    for _ in range(n_steps):
+        for i, b in enumerate(drifts):
+            p_nu -= kicks[i] * eps * g_nu
+            p_u -= kicks[i] * eps * g_u
+            q_nu += b * eps * minv_nu * p_nu
+            q_u += b * eps * minv_u * p_u
+            pot, g_nu, g_u = grad_fn(q_nu, q_u)
+        p_nu -= kicks[-1] * eps * g_nu
+        p_u -= kicks[-1] * eps * g_u
+    h1 = pot + kinetic(p_nu, p_u, minv_nu, minv_u)
+    return q_nu, q_u, p_nu, p_u, h0, h1
