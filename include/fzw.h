@@ -204,6 +204,57 @@ void fzw_dual_avg_init(fzw_dual_avg* state, double eps0, double target);
 double fzw_dual_avg_update(fzw_dual_avg* state, double accept_stat);
 double fzw_dual_avg_final(const fzw_dual_avg* state);
 
+/* Deterministic starting point of every chain (Section 2.2 initialisation):
+ * the tracer contrast delta_tr = n N^3 / N_tr - 1 of the counts set with
+ * fzw_set_counts, Wiener-filtered with the plan's linear spectrum and Poisson
+ * shot noise 1/nbar per cell (nbar = N_tr / N^3), peculiar motions ignored,
+ * and mapped back to white noise: nu_hat = h / (h^2 + 1/nbar) rfft(delta_tr)
+ * with h = sqrt(P/dx^3) and nu_hat(0) = 0.  nu: device float32, packed like
+ * the state of fzw_value_and_grad (written).  FZW_E_STATE if counts are
+ * missing. */
+fzw_status fzw_wiener_start(fzw_plan* plan, float* nu);
+
+/* Validation statistics of fields on one of the plan's meshes (Section 4).
+ * Both overwrite the plan's intermediate fields of that mesh (fzw_get_field
+ * is then stale) and run on the caller's stream.
+ *
+ * fzw_power_multipoles: monopole and quadrupole of the auto (b = NULL) or
+ * cross spectrum of real float32 fields a, b (device, N^3, C order), with
+ * respect to a plane-parallel line of sight along z:
+ *   P_l(k) = (2l+1) < P(k) L_l(mu) >_shell,  mu = k_z / k,
+ *   P(k) = dx^3 / N^3 Re(a_k conj(b_k)) per rfft mode,
+ * over shells [k_lo + i dk, k_lo + (i+1) dk), i < nbins <= 256; a half-
+ * spectrum mode with 0 < n_z < N/2 counts twice.  out: device float64
+ * [nbins][4] = (mean |k|, modes, P0, P2).  Cross-correlation and propagator
+ * follow as P_ab / sqrt(P_aa P_bb) and P_ab / P_bb.
+ *
+ * fzw_bispectrum: bispectrum B and reduced bispectrum
+ * Q = B / (P1 P2 + P2 P3 + P3 P1) of a real float32 field (device, N^3) by the
+ * FFT estimator over shells of width dk centred on k1, k2 and
+ * k3 = sqrt(k1^2 + k2^2 + 2 k1 k2 cos theta) for each opening angle theta
+ * (host float64 [ntheta], ntheta <= 256):
+ *   B = dx^6 / N^3 * sum_x I1 I2 I3 / sum_x J1 J2 J3,
+ * I_i the inverse DFT of the field's spectrum on shell i, J_i that of the
+ * shell's indicator.  out: device float64 [ntheta][4] = (k3, B, Q, closed
+ * triangles).  Returns after the stream has finished. */
+fzw_status fzw_power_multipoles(fzw_plan* plan, int mesh_n, const float* a, const float* b, double k_lo, double dk,
+                                int nbins, double* out);
+fzw_status fzw_bispectrum(fzw_plan* plan, int mesh_n, const float* delta, double k1, double k2, double dk,
+                          int ntheta, const double* theta, double* out);
+
+/* Splitting scheme of fzw_leapfrog's steps (Section 2.2 names second- and
+ * fourth-order HMC and the variant of Blanes, Casas & Sanz-Serna 2014).  One
+ * step with step size eps is K(a_0) D(b_1) K(a_1) ... D(b_m) K(a_m), K(a) the
+ * kick p -= a eps dU/dq, D(b) the drift q += b eps M^-1 p:
+ *   FZW_INT_LEAPFROG  a = (1/2, 1/2), b = (1): one gradient per step (default)
+ *   FZW_INT_BLANES2   a = (0.21178, 0.57644, 0.21178), b = (1/2, 1/2): two
+ *   FZW_INT_YOSHIDA4  three leapfrog steps of w1, w0, w1 eps with
+ *                     w1 = 1/(2 - 2^(1/3)), w0 = 1 - 2 w1 (fourth order): three
+ * Applies to later fzw_leapfrog calls (each scheme has its own graph);
+ * fzw_nuts always uses leapfrog leaves. */
+enum { FZW_INT_LEAPFROG = 0, FZW_INT_BLANES2 = 1, FZW_INT_YOSHIDA4 = 2 };
+fzw_status fzw_set_integrator(fzw_plan* plan, int kind);
+
 /* Copy an intermediate field of the last forward evaluation (device
  * destination, float32 N^3 of one chain).  Fields: 0 delta_L, 1 Psi_x,
  * 2 Psi_y, 3 Psi_z, 4 rho (CIC density, mean 1), 5 log f (log of the

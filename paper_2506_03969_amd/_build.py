@@ -7,7 +7,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libfzw.so")
-SOURCES = ["fzw_fft.hip", "fzw_ops.hip", "fzw_nuts.hip", "fzw_plan.cpp"]
+SOURCES = ["fzw_fft.hip", "fzw_ops.hip", "fzw_nuts.hip", "fzw_stats.hip", "fzw_plan.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          # packed FP32 instructions stay off (see the note in the design doc)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

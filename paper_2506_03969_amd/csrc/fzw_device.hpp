@@ -335,6 +335,46 @@ __device__ __forceinline__ float2 spec_eval(const SpecOp& op, const KVec& kv, fl
   return make_float2(op.re * m, op.im * m);
 }
 
+// Value of radial multiplier t at q = |n|^2: a closed form where one exists
+// (the branch is uniform: t comes from the pass arguments), else the table.
+__device__ __forceinline__ float radial_value(const RadialForms* __restrict__ rf, int t, int q, const float* tabs,
+                                              int tab_stride) {
+  // exp(-c q) as 2^(-c log2(e) q): one multiply and the hardware exp2; its
+  // relative error, a few ulp times c q, stays below 1e-6 wherever the
+  // factor is above 1e-6
+  const int kind = rf->kind[t];
+  if (kind == 0) return tabs[t * tab_stride + min(q, tab_stride - 1)];
+  const float fq = (float)q;
+  const float ik2 = q > 0 ? rf->inv_kf2 * __builtin_amdgcn_rcpf(fq) : 0.f;
+  if (kind == 1) return ik2;
+  const float g = __builtin_amdgcn_exp2f(-rf->c[t] * fq);
+  return kind == 2 ? g : kind == 3 ? 1.f - g : kind == 4 ? g * ik2 : rf->l[t] * g;
+}
+
+template <bool CF>
+__device__ __forceinline__ float2 spec_eval(const SpecOp& op, const KVec& kv, float kf, int nyq,
+                                            const float* tabs, int tab_stride, const RadialForms* rf) {
+  if constexpr (!CF) return spec_eval(op, kv, kf, nyq, tabs, tab_stride);
+  float m = 1.0f;
+  const int a0 = op.ax[0], a1 = op.ax[1];
+  if (a0 >= 0) {
+    const int n0 = kv_axis(kv, a0);
+    if (a0 == a1) {
+      const float k = kf * (float)n0;
+      m *= k * k;
+    } else {
+      m *= (abs(n0) == nyq) ? 0.0f : kf * (float)n0;
+      if (a1 >= 0) {
+        const int n1 = kv_axis(kv, a1);
+        m *= (abs(n1) == nyq) ? 0.0f : kf * (float)n1;
+      }
+    }
+  }
+  if (op.tb[0] >= 0) m *= radial_value(rf, op.tb[0], kv.n2, tabs, tab_stride);
+  if (op.tb[1] >= 0) m *= radial_value(rf, op.tb[1], kv.n2, tabs, tab_stride);
+  return make_float2(op.re * m, op.im * m);
+}
+
 // A multiplier with no wave-number or table factor: a plain constant.
 __device__ __forceinline__ bool spec_is_const(const SpecOp& op) {
   return op.ax[0] < 0 && op.tb[0] < 0 && op.tb[1] < 0;

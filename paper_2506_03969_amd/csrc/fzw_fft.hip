@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kThreadsXY) void xy_pass_kernel(PassArgs a, const f
             kv.n[1] = AXIS == 0 ? nb : nr;
             kv.n[2] = nz;
             kv.n2 = kv.n[0] * kv.n[0] + kv.n[1] * kv.n[1] + nz * nz;
-            const float2 w = spec_eval(op, kv, a.kf, nyq, a.tabs, a.tab_stride);
+            const float2 w = spec_eval<true>(op, kv, a.kf, nyq, a.tabs, a.tab_stride, a.rf);
             mid[m][j] = cadd(mid[m][j], cmul(w, val[j]));
           }
         }
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kThreadsXY) void xy_pass_kernel(PassArgs a, const f
             kv.n[1] = AXIS == 0 ? nb : nr;
             kv.n[2] = nz;
             kv.n2 = kv.n[0] * kv.n[0] + kv.n[1] * kv.n[1] + nz * nz;
-            const float2 w = spec_eval(op, kv, a.kf, nyq, a.tabs, a.tab_stride);
+            const float2 w = spec_eval<true>(op, kv, a.kf, nyq, a.tabs, a.tab_stride, a.rf);
             val[j] = cadd(val[j], cmul(w, mid[m][j]));
           }
         }
@@ -495,7 +495,7 @@ __host__ __device__ constexpr int xy4_cols() {
 
 // Used for single-mix passes (NMID = 1), where three workgroups per CU fit in
 // registers without spilling; multi-mix passes use the Stockham kernel.
-template <int N, int AXIS, int NMID>
+template <int N, int AXIS, int NMID, bool PF>
 __global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1, 3) void xy4_pass_kernel(PassArgs a, const float2* __restrict__ twg) {
   constexpr int N1 = F4<N>::N1, N2 = F4<N>::N2;
   constexpr int M = N / 2;
@@ -546,16 +546,23 @@ __global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1, 3) void xy4_pass_kernel(
     }
   };
   // with several inputs, the loads of input i+1 are in flight during the
-  // transform of input i
-  const bool pf = a.nin > 1;
-  float2 nxt[N2];
-  if (pf) load_input(0, nxt);
+  // transform of input i (the single-input variant has no prefetch registers
+  // and evaluates the radial multipliers in closed form)
+  float2 nxt[PF ? N2 : 1];
+  const bool pf = PF && a.nin > 1;
+  if constexpr (PF) {
+    if (pf) load_input(0, nxt);
+  }
   for (int i = 0; i < a.nin; ++i) {
     float2 val[N2];
-    if (pf) {
+    if constexpr (PF) {
+      if (pf) {
 #pragma unroll
-      for (int e = 0; e < N2; ++e) val[e] = nxt[e];
-      if (i + 1 < a.nin) load_input(i + 1, nxt);
+        for (int e = 0; e < N2; ++e) val[e] = nxt[e];
+        if (i + 1 < a.nin) load_input(i + 1, nxt);
+      } else {
+        load_input(i, val);
+      }
     } else {
       load_input(i, val);
     }
@@ -578,7 +585,7 @@ __global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1, 3) void xy4_pass_kernel(
         kv.n[1] = AXIS == 0 ? nb : nr;
         kv.n[2] = nz;
         kv.n2 = kv.n[0] * kv.n[0] + kv.n[1] * kv.n[1] + nz * nz;
-        mid[m][e] = cadd(mid[m][e], cmul(spec_eval(op, kv, a.kf, nyq, a.tabs, a.tab_stride), val[e]));
+        mid[m][e] = cadd(mid[m][e], cmul(spec_eval<!PF>(op, kv, a.kf, nyq, a.tabs, a.tab_stride, a.rf), val[e]));
       }
     }
   }
@@ -615,7 +622,7 @@ __global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1, 3) void xy4_pass_kernel(
         kv.n[1] = AXIS == 0 ? nb : nr;
         kv.n[2] = nz;
         kv.n2 = kv.n[0] * kv.n[0] + kv.n[1] * kv.n[1] + nz * nz;
-        val[e] = cadd(val[e], cmul(spec_eval(op, kv, a.kf, nyq, a.tabs, a.tab_stride), mid[m][e]));
+        val[e] = cadd(val[e], cmul(spec_eval<!PF>(op, kv, a.kf, nyq, a.tabs, a.tab_stride, a.rf), mid[m][e]));
       }
     }
     if (!have) {
@@ -901,8 +908,14 @@ static void xyp4(int axis, const PassArgs& a, int chains, const float2* tw, hipS
   constexpr int C = xy4_cols<N>();
   dim3 grid((N / 2 + 1 + C - 1) / C, N, chains);
   dim3 block(C * F4<N>::N1);
-  if (axis == 0) hipLaunchKernelGGL((xy4_pass_kernel<N, 0, 1>), grid, block, 0, s, a, tw);
-  else hipLaunchKernelGGL((xy4_pass_kernel<N, 1, 1>), grid, block, 0, s, a, tw);
+  const bool pf = a.nin > 1;
+  if (axis == 0) {
+    if (pf) hipLaunchKernelGGL((xy4_pass_kernel<N, 0, 1, true>), grid, block, 0, s, a, tw);
+    else hipLaunchKernelGGL((xy4_pass_kernel<N, 0, 1, false>), grid, block, 0, s, a, tw);
+  } else {
+    if (pf) hipLaunchKernelGGL((xy4_pass_kernel<N, 1, 1, true>), grid, block, 0, s, a, tw);
+    else hipLaunchKernelGGL((xy4_pass_kernel<N, 1, 1, false>), grid, block, 0, s, a, tw);
+  }
 }
 
 template <int N>

@@ -31,6 +31,19 @@ constexpr int kMaxOut = 6;
 // `in_fft` is set) and mixed: mid[m] = sum_i A[m][i] X_i.
 // Phase 2: out[o] = B[o] . mid, inverse-transformed along the axis if its bit
 // in `out_fft` is set, then stored.
+// Radial multipliers with a closed form in |n|^2 = q, evaluated in registers
+// instead of gathered from the tables: kind 0 looks the table up; 1: 1/k^2;
+// 2: 2^(-c q); 3: 1 - 2^(-c q); 4: 2^(-c q)/k^2; 5: l 2^(-c q), with
+// k^2 = kf^2 q (and 0 for the 1/k^2 forms at q = 0); c holds the Gaussian's
+// k^2 r^2 / 2 coefficient divided by ln 2.
+constexpr int kRadialTables = 6;
+struct RadialForms {
+  signed char kind[kRadialTables];
+  float c[kRadialTables];
+  float l[kRadialTables];
+  float inv_kf2;
+};
+
 struct PassArgs {
   const float2* in[kMaxIn];
   float2* out[kMaxOut];
@@ -42,6 +55,7 @@ struct PassArgs {
   const float* tabs;          // radial tables [ntab][tab_stride]
   int tab_stride;
   float kf;                   // 2 pi / L
+  const RadialForms* rf;      // tables evaluated in closed form instead of looked up (device)
 };
 
 // The z transforms around the LPT pointwise step, fused with it (see

@@ -1058,9 +1058,9 @@ __global__ void kick_kernel(LeapArgs a, float frac) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.nv; i += (long long)gridDim.x * blockDim.x)
     a.p[o + i] -= e * (a.q[o + i] - a.g[o + i]);
 }
-__global__ void drift_kernel(LeapArgs a) {
+__global__ void drift_kernel(LeapArgs a, float frac) {
   const long long c = blockIdx.y;
-  const float e = a.step[a.chain0 + c];
+  const float e = a.step[a.chain0 + c] * frac;
   const long long o = c * a.nv;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.nv; i += (long long)gridDim.x * blockDim.x)
     a.q[o + i] += e * a.minv[o + i] * a.p[o + i];
@@ -1081,8 +1081,8 @@ __global__ void energy_kernel(LeapArgs a) {
 void launch_kick(const LeapArgs& a, int chains, float frac, hipStream_t s) {
   hipLaunchKernelGGL(kick_kernel, dim3(grid_for(a.nv, 256, 4096), chains), dim3(256), 0, s, a, frac);
 }
-void launch_drift(const LeapArgs& a, int chains, hipStream_t s) {
-  hipLaunchKernelGGL(drift_kernel, dim3(grid_for(a.nv, 256, 4096), chains), dim3(256), 0, s, a);
+void launch_drift(const LeapArgs& a, int chains, float frac, hipStream_t s) {
+  hipLaunchKernelGGL(drift_kernel, dim3(grid_for(a.nv, 256, 4096), chains), dim3(256), 0, s, a, frac);
 }
 void launch_energy(const LeapArgs& a, int chains, int nblk, hipStream_t s) {
   hipLaunchKernelGGL(energy_kernel, dim3(nblk, chains), dim3(256), 0, s, a);
@@ -1091,7 +1091,7 @@ void launch_energy(const LeapArgs& a, int chains, int nblk, hipStream_t s) {
 // Free bias parameters: one workgroup per chain.
 //   mode 0: table = base with tied entries exp(u)
 //   mode 1: half kick of p_u with frac * step
-//   mode 2: drift of u
+//   mode 2: drift of u with frac * step
 //   mode 3: Hamiltonian: H = -logL + field energy partials + prior + kinetic(u)
 __global__ void params_kernel(ParamArgs a, int mode, float frac, int nblk_energy, double* hout) {
   const int c = blockIdx.x;
@@ -1114,7 +1114,7 @@ __global__ void params_kernel(ParamArgs a, int mode, float frac, int nblk_energy
       pu[f] -= e * (float)du;
     }
   } else if (mode == 2) {
-    const float e = a.step[c];
+    const float e = a.step[c] * frac;
     for (int f = threadIdx.x; f < nf; f += blockDim.x) u[f] += e * mi[f] * pu[f];
   } else {
     if (threadIdx.x == 0) {
@@ -1140,6 +1140,51 @@ __global__ void trace3_kernel(const float* a, const float* b, const float* c, fl
 }
 void launch_trace3(const float* a, const float* b, const float* c, float* out, long long n, hipStream_t s) {
   hipLaunchKernelGGL(trace3_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, a, b, c, out, n);
+}
+
+// Wiener-filter start (Section 2.2 initialisation).  Tracer contrast
+// delta_tr = n N^3 / N_tr - 1 per chain (grid.y = chain).
+__global__ void wiener_contrast_kernel(const uint16_t* __restrict__ counts, const double* __restrict__ scal,
+                                       int chain0, long long nv, float* __restrict__ out) {
+  const long long c = blockIdx.y;
+  const double scale = (double)nv / scal[(chain0 + c) * kScalStride + kScalNtr];
+  const uint16_t* cn = counts + c * nv;
+  float* o = out + c * nv;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x)
+    o[i] = (float)((double)cn[i] * scale - 1.0);
+}
+// nu_hat = h / (h^2 + 1/nbar) delta_tr_hat / N^3 on the padded half spectrum
+// [n][n][pitch] (the 1/N^3 of the inverse transform folded in); h is the
+// white-noise filter tabulated by integer |n|^2.
+__global__ void wiener_filter_kernel(float2* __restrict__ spec, const float* __restrict__ htab, int n, int pitch,
+                                     const double* __restrict__ scal, int chain0, long long nv, long long per_chain) {
+  const long long c = blockIdx.y;
+  const double inv_nbar = (double)nv / scal[(chain0 + c) * kScalStride + kScalNtr];
+  const int m1 = n / 2 + 1;
+  float2* sp = spec + c * per_chain;
+  const long long rows = (long long)n * n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < rows * m1; i += (long long)gridDim.x * blockDim.x) {
+    const long long r = i / m1;
+    const int z = (int)(i - r * m1);
+    const int x = (int)(r / n), y = (int)(r - (long long)x * n);
+    const int nx = x <= n / 2 ? x : x - n, ny = y <= n / 2 ? y : y - n;
+    const float h = htab[nx * nx + ny * ny + z * z];
+    const double f = h > 0.f ? (double)h / ((double)h * h + inv_nbar) / (double)nv : 0.0;
+    float2& v = sp[r * pitch + z];
+    v.x = (float)(v.x * f);
+    v.y = (float)(v.y * f);
+  }
+}
+void launch_wiener_contrast(const uint16_t* counts, const double* scal, int chain0, int chains, long long nv,
+                            float* out, hipStream_t s) {
+  hipLaunchKernelGGL(wiener_contrast_kernel, dim3(grid_for(nv, 256, 4096), chains), dim3(256), 0, s, counts, scal,
+                     chain0, nv, out);
+}
+void launch_wiener_filter(float2* spec, const float* htab, int n, int pitch, const double* scal, int chain0,
+                          int chains, long long per_chain, hipStream_t s) {
+  const long long nv = (long long)n * n * n;
+  hipLaunchKernelGGL(wiener_filter_kernel, dim3(grid_for((long long)n * n * (n / 2 + 1), 256, 4096), chains),
+                     dim3(256), 0, s, spec, htab, n, pitch, scal, chain0, nv, per_chain);
 }
 
 // Copy of a padded half spectrum into the dense [n][n][n/2+1] layout and back.

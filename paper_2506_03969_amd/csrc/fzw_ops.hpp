@@ -217,10 +217,24 @@ void launch_likelihood(const LikeArgs& a, int chains, int nblk, hipStream_t s);
 void launch_finalize(const FinalArgs& a, int chains, hipStream_t s);
 void launch_count_consts(const uint16_t* cnt, long long nv, double* partial, int nblk, double* scal, hipStream_t s);
 void launch_kick(const LeapArgs& a, int chains, float frac, hipStream_t s);
-void launch_drift(const LeapArgs& a, int chains, hipStream_t s);
+void launch_drift(const LeapArgs& a, int chains, float frac, hipStream_t s);
 void launch_energy(const LeapArgs& a, int chains, int nblk, hipStream_t s);
 void launch_params(const ParamArgs& a, int chains, int mode, float frac, int nblk_energy, double* hout, hipStream_t s);
 void launch_trace3(const float* a, const float* b, const float* c, float* out, long long n, hipStream_t s);
+void launch_wiener_contrast(const uint16_t* counts, const double* scal, int chain0, int chains, long long nv,
+                            float* out, hipStream_t s);
+void launch_wiener_filter(float2* spec, const float* htab, int n, int pitch, const double* scal, int chain0,
+                          int chains, long long per_chain, hipStream_t s);
+int stats_blocks();
+void launch_multipoles(const float2* a, const float2* b, int n, int pitch, double kf, double k_lo, double dk,
+                       int nbins, double pnorm, double* partial, double* out, hipStream_t s);
+void launch_shell(const float2* src, float2* dst, int n, int pitch, double kf, double lo, double hi, hipStream_t s);
+void launch_triple_sum(const float* a, const float* b, const float* c, long long nv, double* partial, double* dst,
+                       hipStream_t s);
+void launch_shell_power(const float2* d, int n, int pitch, double kf, double lo, double hi, double* partial,
+                        double* dst, hipStream_t s);
+void launch_bispectrum_final(const double* sc, const double* p12, const double* k3, int ntheta, int n, double dx,
+                             double* out, hipStream_t s);
 void launch_spec_repack(const float2* src, float2* dst, int n, int sp, int dp, long long rows, hipStream_t s);
 
 }  // namespace fzw

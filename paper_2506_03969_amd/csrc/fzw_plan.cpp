@@ -41,6 +41,7 @@ struct Error : std::runtime_error {
 
 // radial tables
 enum { TAB_H = 0, TAB_INVK2 = 1, TAB_K = 2, TAB_1MK = 3, TAB_WEB0 = 4, TAB_WEB1 = 5, NTAB = 6 };
+static_assert(NTAB == kRadialTables, "one closed form per table");
 // stage scratch spectra
 constexpr int kNSpec = 13;
 
@@ -87,6 +88,8 @@ struct Group {
   hipEvent_t gdone = nullptr;
   float* tabs = nullptr;
   int tab_stride = 0;
+  RadialForms rf{};          // closed forms of the tables (all but h(k))
+  RadialForms* rf_dev = nullptr;   // device copy read by the passes
   float2* tw_full = nullptr;
   float2* tw_half = nullptr;
   // real fields [nc][nv]
@@ -170,6 +173,8 @@ struct fzw_plan {
   double* nuts_partial = nullptr;
   int* nuts_any = nullptr;
   int* nuts_any_host = nullptr;       // pinned
+  double* stats_buf = nullptr;        // partials and scalars of the validation statistics
+  int integrator = FZW_INT_LEAPFROG;  // splitting scheme of fzw_leapfrog
 };
 
 namespace {
@@ -266,6 +271,33 @@ void build_tables(fzw_plan* p, Group& g) {
       tab[(size_t)(TAB_WEB0 + w) * g.tab_stride + q] = (float)m;
     }
   }
+  // closed forms of every table but h(k) (BBKS), evaluated in FP32 in the
+  // passes; FZW_RADIAL_FORMS=0 keeps every table a lookup
+  const char* env = std::getenv("FZW_RADIAL_FORMS");
+  const bool forms = !(env && env[0] == '0');
+  g.rf = RadialForms{};
+  g.rf.inv_kf2 = (float)(1.0 / (kf * kf));
+  if (forms) {
+    // coefficients of exp(-k^2 r^2 / 2) written as 2^(-c q), q = |n|^2
+    const double cs = 0.5 * kf * kf * p->cosmo.r_s * p->cosmo.r_s / std::log(2.0);
+    g.rf.kind[TAB_INVK2] = 1;
+    g.rf.kind[TAB_K] = 2;
+    g.rf.c[TAB_K] = (float)cs;
+    g.rf.kind[TAB_1MK] = 3;
+    g.rf.c[TAB_1MK] = (float)cs;
+    for (int w = 0; w < p->W; ++w) {
+      const double r = p->web.smooth_r[w];
+      g.rf.c[TAB_WEB0 + w] = (float)(0.5 * kf * kf * r * r / std::log(2.0));
+      if (p->web.kind[w] == FZW_WEB_PHI) {
+        g.rf.kind[TAB_WEB0 + w] = 4;
+      } else {
+        g.rf.kind[TAB_WEB0 + w] = 5;
+        g.rf.l[TAB_WEB0 + w] = (float)(p->web.ell[w] * p->web.ell[w]);
+      }
+    }
+  }
+  g.rf_dev = dalloc<RadialForms>(p, 1);
+  HIPCHK(hipMemcpy(g.rf_dev, &g.rf, sizeof(RadialForms), hipMemcpyHostToDevice));
   g.tabs = dalloc<float>(p, tab.size());
   HIPCHK(hipMemcpy(g.tabs, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice));
   std::vector<float2> tf(n), th(half);
@@ -339,6 +371,7 @@ void run_pass(const Group& g, int axis, Pass& ps, int nmid, hipStream_t s) {
   ps.a.tabs = g.tabs;
   ps.a.tab_stride = g.tab_stride;
   ps.a.kf = (float)(2.0 * M_PI / g.box);
+  ps.a.rf = g.rf_dev;
   launch_xy_pass(g.n, axis, ps.a, g.nc, g.tw_full, s);
 }
 
@@ -902,6 +935,7 @@ void free_plan(fzw_plan* p) {
   if (p->nuts_partial) (void)hipFree(p->nuts_partial);
   if (p->nuts_any) (void)hipFree(p->nuts_any);
   if (p->nuts_any_host) (void)hipHostFree(p->nuts_any_host);
+  if (p->stats_buf) (void)hipFree(p->stats_buf);
   for (auto e : p->evpool) (void)hipEventDestroy(e);
   delete p;
 }
@@ -1218,6 +1252,27 @@ fzw_status fzw_set_sampling(fzw_plan* p, const int* tie, int n_free, const doubl
   });
 }
 
+// Splitting schemes of one integration step, K(a_0) D(b_1) K(a_1) ... D(b_m)
+// K(a_m), the gradient evaluated after every drift (Section 2.2 names
+// second- and fourth-order HMC and the variant of Blanes, Casas & Sanz-Serna
+// 2014): kick-drift-kick; the two-stage splitting with b = 0.21178; three
+// leapfrog steps of w1, w0, w1 with w1 = 1/(2 - 2^(1/3)), w0 = 1 - 2 w1
+// (Yoshida 1990), adjacent kicks merged.
+struct Scheme {
+  int stages;
+  double kick[4];
+  double drift[3];
+};
+
+static const Scheme& scheme_of(int kind) {
+  static const Scheme lf = {1, {0.5, 0.5}, {1.0}};
+  static const double b = 0.21178;
+  static const Scheme bl = {2, {b, 1.0 - 2.0 * b, b}, {0.5, 0.5}};
+  static const double w1 = 1.0 / (2.0 - std::cbrt(2.0)), w0 = 1.0 - 2.0 * w1;
+  static const Scheme y4 = {3, {0.5 * w1, 0.5 * (w1 + w0), 0.5 * (w0 + w1), 0.5 * w1}, {w1, w0, w1}};
+  return kind == FZW_INT_BLANES2 ? bl : kind == FZW_INT_YOSHIDA4 ? y4 : lf;
+}
+
 static void enqueue_trajectory(fzw_plan* p, float* nu, float* u, float* p_nu, float* p_u, const float* base,
                                const float* minv_nu, const float* minv_u, const float* step, int n_steps,
                                double* h_start, double* h_end) {
@@ -1258,16 +1313,21 @@ static void enqueue_trajectory(fzw_plan* p, float* nu, float* u, float* p_nu, fl
     for (auto& g : p->groups) launch_energy(leap(g), g.nc, kEBlk, s);
     launch_params(pa, C, 3, 0.f, kEBlk, h, s);
   };
+  const Scheme& sc = scheme_of(p->integrator);
+  auto kick = [&](double a) {
+    for (auto& g : p->groups) launch_kick(leap(g), g.nc, (float)a, s);
+    launch_params(pa, C, 1, (float)a, kEBlk, nullptr, s);
+  };
   grad();
   hamiltonian(h_start);
   for (int it = 0; it < n_steps; ++it) {
-    for (auto& g : p->groups) launch_kick(leap(g), g.nc, 0.5f, s);
-    launch_params(pa, C, 1, 0.5f, kEBlk, nullptr, s);
-    for (auto& g : p->groups) launch_drift(leap(g), g.nc, s);
-    launch_params(pa, C, 2, 0.f, kEBlk, nullptr, s);
-    grad();
-    for (auto& g : p->groups) launch_kick(leap(g), g.nc, 0.5f, s);
-    launch_params(pa, C, 1, 0.5f, kEBlk, nullptr, s);
+    for (int i = 0; i < sc.stages; ++i) {
+      kick(sc.kick[i]);
+      for (auto& g : p->groups) launch_drift(leap(g), g.nc, (float)sc.drift[i], s);
+      launch_params(pa, C, 2, (float)sc.drift[i], kEBlk, nullptr, s);
+      grad();
+    }
+    kick(sc.kick[sc.stages]);
   }
   hamiltonian(h_end);
 }
@@ -1285,7 +1345,8 @@ fzw_status fzw_leapfrog(fzw_plan* p, float* nu, float* u, float* p_nu, float* p_
     if (p->nfree > 0 && (!u || !p_u || !minv_u)) throw Error(FZW_E_ARG, "u, p_u, minv_u required");
     std::vector<uintptr_t> key = {(uintptr_t)nu, (uintptr_t)u, (uintptr_t)p_nu, (uintptr_t)p_u,
                                   (uintptr_t)bias_base, (uintptr_t)minv_nu, (uintptr_t)minv_u,
-                                  (uintptr_t)step, (uintptr_t)n_steps, (uintptr_t)h_start, (uintptr_t)h_end};
+                                  (uintptr_t)step, (uintptr_t)n_steps, (uintptr_t)h_start, (uintptr_t)h_end,
+                                  (uintptr_t)p->integrator};
     auto it = p->graphs.find(key);
     // order the private stream after the caller's work
     HIPCHK(hipEventRecord(p->ev_in, p->user_stream));
@@ -1379,6 +1440,139 @@ double fzw_dual_avg_update(fzw_dual_avg* s, double accept_stat) {
 }
 
 double fzw_dual_avg_final(const fzw_dual_avg* s) { return std::exp(s->log_eps_bar); }
+
+// ------------------------------------------------------ validation statistics
+constexpr int kStatsMaxBins = 256;
+constexpr int kStatsMaxTheta = 256;
+
+static double* stats_buffer(fzw_plan* p) {
+  if (!p->stats_buf) {
+    const size_t n = (size_t)stats_blocks() * kStatsMaxBins * 4 + 4 * kStatsMaxTheta + 4 + kStatsMaxTheta;
+    HIPCHK(hipMalloc(&p->stats_buf, n * sizeof(double)));
+  }
+  return p->stats_buf;
+}
+
+static Group stats_group(fzw_plan* p, int n) {
+  for (auto& g : p->groups)
+    if (g.n == n) {
+      Group one = g;
+      one.nc = 1;
+      return one;
+    }
+  throw Error(FZW_E_SIZE, "mesh size not in plan");
+}
+
+static void forward_spectrum(const Group& g, const float* x, float2* out, hipStream_t s) {
+  float* src[1] = {const_cast<float*>(x)};
+  float2* dst[1] = {out};
+  zf(g, src, dst, 1, s);
+  pure_pass(g, Y, false, dst, 1, s);
+  pure_pass(g, X, false, dst, 1, s);
+}
+
+fzw_status fzw_power_multipoles(fzw_plan* p, int mesh_n, const float* a, const float* b, double k_lo, double dk,
+                                int nbins, double* out) {
+  if (!p || !a || !out || !(dk > 0) || nbins < 1 || nbins > kStatsMaxBins) {
+    g_last_error = "fzw_power_multipoles: bad argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    t_plan = p;
+    Group g = stats_group(p, mesh_n);
+    hipStream_t s = p->stream;
+    double* buf = stats_buffer(p);
+    forward_spectrum(g, a, g.spec[0], s);
+    if (b) forward_spectrum(g, b, g.spec[1], s);
+    const double dx = g.box / g.n;
+    const double pnorm = dx * dx * dx / ((double)g.n * g.n * g.n);
+    launch_multipoles(g.spec[0], b ? g.spec[1] : g.spec[0], g.n, g.P, 2.0 * M_PI / g.box, k_lo, dk, nbins, pnorm,
+                      buf, out, s);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+fzw_status fzw_bispectrum(fzw_plan* p, int mesh_n, const float* delta, double k1, double k2, double dk, int ntheta,
+                          const double* theta, double* out) {
+  if (!p || !delta || !theta || !out || !(dk > 0) || !(k1 > 0) || !(k2 > 0) || ntheta < 1 ||
+      ntheta > kStatsMaxTheta) {
+    g_last_error = "fzw_bispectrum: bad argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    t_plan = p;
+    Group g = stats_group(p, mesh_n);
+    hipStream_t s = p->stream;
+    double* buf = stats_buffer(p);
+    double* partial = buf;
+    double* sc = buf + (size_t)stats_blocks() * kStatsMaxBins * 4;   // [ntheta][4]
+    double* p12 = sc + 4 * kStatsMaxTheta;                            // [4]
+    double* k3d = p12 + 4;                                            // [ntheta]
+    const double kf = 2.0 * M_PI / g.box;
+    std::vector<double> k3(ntheta);
+    for (int t = 0; t < ntheta; ++t) k3[t] = std::sqrt(k1 * k1 + k2 * k2 + 2.0 * k1 * k2 * std::cos(theta[t]));
+    HIPCHK(hipMemcpyAsync(k3d, k3.data(), sizeof(double) * ntheta, hipMemcpyHostToDevice, s));
+    forward_spectrum(g, delta, g.spec[0], s);
+    auto shell_field = [&](double kc, bool indicator, float* dst) {
+      launch_shell(indicator ? nullptr : g.spec[0], g.spec[1], g.n, g.P, kf, kc - 0.5 * dk, kc + 0.5 * dk, s);
+      float2* sp[1] = {g.spec[1]};
+      pure_pass(g, X, true, sp, 1, s);
+      pure_pass(g, Y, true, sp, 1, s);
+      float* d[1] = {dst};
+      zi(g, sp, d, 1, s);
+    };
+    float *i1 = g.phi[0], *j1 = g.phi[1], *i2 = g.phi[2], *j2 = g.phi[3], *i3 = g.phi[4], *j3 = g.phi[5];
+    shell_field(k1, false, i1);
+    shell_field(k1, true, j1);
+    shell_field(k2, false, i2);
+    shell_field(k2, true, j2);
+    launch_shell_power(g.spec[0], g.n, g.P, kf, k1 - 0.5 * dk, k1 + 0.5 * dk, partial, p12, s);
+    launch_shell_power(g.spec[0], g.n, g.P, kf, k2 - 0.5 * dk, k2 + 0.5 * dk, partial, p12 + 2, s);
+    for (int t = 0; t < ntheta; ++t) {
+      shell_field(k3[t], false, i3);
+      shell_field(k3[t], true, j3);
+      launch_triple_sum(i1, i2, i3, g.nv, partial, sc + 4 * t, s);
+      launch_triple_sum(j1, j2, j3, g.nv, partial, sc + 4 * t + 1, s);
+      launch_shell_power(g.spec[0], g.n, g.P, kf, k3[t] - 0.5 * dk, k3[t] + 0.5 * dk, partial, sc + 4 * t + 2, s);
+    }
+    launch_bispectrum_final(sc, p12, k3d, ntheta, g.n, g.box / g.n, out, s);
+    HIPCHK(hipStreamSynchronize(s));   // k3 lives on the host stack
+  });
+}
+
+fzw_status fzw_wiener_start(fzw_plan* p, float* nu) {
+  if (!p || !nu) {
+    g_last_error = "fzw_wiener_start: bad argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    check_ready(p);
+    t_plan = p;
+    hipStream_t s = p->stream;
+    for (auto& g : p->groups) {
+      float* out = nu + p->chain_off[g.c0];
+      launch_wiener_contrast(p->counts + p->chain_off[g.c0], p->scal, g.c0, g.nc, g.nv, out, s);
+      float* io[1] = {out};
+      zf(g, io, &g.spec[0], 1, s);
+      pure_pass(g, Y, false, &g.spec[0], 1, s);
+      pure_pass(g, X, false, &g.spec[0], 1, s);
+      launch_wiener_filter(g.spec[0], g.tabs + (size_t)TAB_H * g.tab_stride, g.n, g.P, p->scal, g.c0, g.nc, g.ns, s);
+      pure_pass(g, X, true, &g.spec[0], 1, s);
+      pure_pass(g, Y, true, &g.spec[0], 1, s);
+      zi(g, &g.spec[0], io, 1, s);
+    }
+    HIPCHK(hipGetLastError());
+  });
+}
+
+fzw_status fzw_set_integrator(fzw_plan* p, int kind) {
+  if (!p || kind < FZW_INT_LEAPFROG || kind > FZW_INT_YOSHIDA4) {
+    g_last_error = "fzw_set_integrator: bad argument";
+    return FZW_E_ARG;
+  }
+  p->integrator = kind;
+  return FZW_OK;
+}
 
 fzw_status fzw_get_field(fzw_plan* p, int chain, int field, float* out) {
   if (!p || !out || chain < 0 || chain >= p->n_chains || field < 0 || field >= 6 + 6 * p->W) {

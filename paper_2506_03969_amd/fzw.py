@@ -96,6 +96,10 @@ def load_library(path: str = _LIB_PATH):
     lib.fzw_nuts.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i, vp, vp, vp]
     ll = ctypes.c_longlong
     lib.fzw_welford.argtypes = [vp, vp, vp, vp, ll, i]
+    lib.fzw_wiener_start.argtypes = [vp, vp]
+    lib.fzw_set_integrator.argtypes = [vp, i]
+    lib.fzw_power_multipoles.argtypes = [vp, i, vp, vp, d, d, i, vp]
+    lib.fzw_bispectrum.argtypes = [vp, i, vp, d, d, d, i, ctypes.POINTER(d), vp]
     lib.fzw_inverse_mass.argtypes = [vp, vp, vp, ll, i]
     lib.fzw_dual_avg_init.argtypes = [ctypes.POINTER(CDualAvg), d, d]
     lib.fzw_dual_avg_init.restype = None
@@ -105,7 +109,8 @@ def load_library(path: str = _LIB_PATH):
     lib.fzw_dual_avg_final.restype = d
     for name in ("fzw_plan_create", "fzw_set_counts", "fzw_forward", "fzw_value_and_grad",
                  "fzw_set_sampling", "fzw_leapfrog", "fzw_get_field", "fzw_fft_r2c", "fzw_fft_c2r",
-                 "fzw_nuts", "fzw_welford", "fzw_inverse_mass"):
+                 "fzw_nuts", "fzw_welford", "fzw_inverse_mass", "fzw_wiener_start", "fzw_power_multipoles",
+                 "fzw_bispectrum", "fzw_set_integrator"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -266,6 +271,33 @@ class Plan:
                "fzw_nuts")
         return pot, acc, stats
 
+    def wiener_start(self, nu=None):
+        """White-noise start of every chain from its Wiener-filtered counts
+        (fzw_wiener_start); returns the packed field."""
+        if nu is None:
+            nu = torch.empty(self.total_voxels, dtype=torch.float32, device=self.device)
+        _check(_lib.fzw_wiener_start(self._h, _ptr(nu, torch.float32)), "fzw_wiener_start")
+        return nu
+
+    def power_multipoles(self, a, b=None, k_lo=0.0, dk=None, nbins=32, mesh_n=None):
+        """Monopole and quadrupole of the auto or cross spectrum of fields on
+        one of the plan's meshes: tensor [nbins][4] = (k, modes, P0, P2)."""
+        n = mesh_n or round(a.numel() ** (1.0 / 3.0))
+        out = torch.empty((nbins, 4), dtype=torch.float64, device=self.device)
+        _check(_lib.fzw_power_multipoles(self._h, int(n), _ptr(a, torch.float32), _ptr(b, torch.float32),
+                                         float(k_lo), float(dk), int(nbins), _ptr(out, torch.float64)),
+               "fzw_power_multipoles")
+        return out
+
+    def bispectrum(self, delta, k1, k2, dk, thetas, mesh_n=None):
+        """(k3, B, Q, triangles) per opening angle: tensor [len(thetas)][4]."""
+        n = mesh_n or round(delta.numel() ** (1.0 / 3.0))
+        th = (ctypes.c_double * len(thetas))(*[float(t) for t in thetas])
+        out = torch.empty((len(thetas), 4), dtype=torch.float64, device=self.device)
+        _check(_lib.fzw_bispectrum(self._h, int(n), _ptr(delta, torch.float32), float(k1), float(k2), float(dk),
+                                   len(thetas), th, _ptr(out, torch.float64)), "fzw_bispectrum")
+        return out
+
     def welford(self, x, mean, m2, count):
         """Adds sample `count` (1-based) x to the running mean and m2."""
         _check(_lib.fzw_welford(self._h, _ptr(x, torch.float32), _ptr(mean, torch.float32), _ptr(m2, torch.float32),
@@ -274,6 +306,14 @@ class Plan:
     def inverse_mass(self, m2, minv, count):
         _check(_lib.fzw_inverse_mass(self._h, _ptr(m2, torch.float32), _ptr(minv, torch.float32), m2.numel(),
                                      int(count)), "fzw_inverse_mass")
+
+    INTEGRATORS = {"leapfrog": 0, "blanes2": 1, "yoshida4": 2}
+
+    def set_integrator(self, scheme: str):
+        """Splitting scheme of `leapfrog` trajectories: 'leapfrog' (default),
+        'blanes2' (two-stage, two gradients per step) or 'yoshida4' (fourth
+        order, three gradients per step)."""
+        _check(_lib.fzw_set_integrator(self._h, self.INTEGRATORS[scheme]), "fzw_set_integrator")
 
     def set_cic_method(self, method: str):
         """'sorted' (counting sort + gather, default) or 'atomic' (fixed-point

@@ -46,19 +46,23 @@ def _setup(name, n):
     return w, m, counts, nu, u0, p_nu, p_u, mu, sig
 
 
+@pytest.mark.parametrize("scheme", ["leapfrog", "blanes2", "yoshida4"])
 @pytest.mark.parametrize("case", [("c0fd", None), ("c2", 32)])
-def test_leapfrog_matches_oracle(case):
+def test_leapfrog_matches_oracle(case, scheme):
+    """A graph-captured trajectory of each splitting scheme against the
+    oracle's integrator: H at both ends to 1e-6 relative, end state 1e-4."""
     name, n = case
     w, m, counts, nu, u0, p_nu, p_u, mu, sig = _setup(name, n)
     ch = w.chains[0]
     eps, steps = 2e-3, 4
     minv_u = np.full(u0.shape, 1e-2)
     gfn = lambda q, u: hmc.potential_and_grad(m, q, u, ch.bias, w.free, mu, sig, counts)
-    q1, u1, p1, pu1, h0, h1 = hmc.leapfrog(gfn, nu, u0, p_nu, p_u, 1.0, minv_u, eps, steps)
+    q1, u1, p1, pu1, h0, h1 = hmc.integrate(gfn, nu, u0, p_nu, p_u, 1.0, minv_u, eps, steps, scheme)
 
     plan = plan_for(w)
     plan.set_counts(0, dev_counts(counts))
     plan.set_sampling(_tie(w), mu, sig)
+    plan.set_integrator(scheme)
     t_nu, t_u = dev(nu.ravel()), dev(u0[None])
     t_p, t_pu = dev(p_nu.ravel()), dev(p_u[None])
     base = dev(ch.bias[None])
@@ -70,7 +74,7 @@ def test_leapfrog_matches_oracle(case):
     e_q = relnorm(host(t_nu).reshape(nu.shape) - nu, q1 - nu)
     e_p = relnorm(host(t_p).reshape(nu.shape), p1)
     e_u = float(np.max(np.abs(host(t_u)[0] - u1)))
-    print(name, n, "H0 %.6e/%.6e H1 %.6e/%.6e dH gpu %.4e oracle %.4e  dq %.2e dp %.2e du %.2e" % (
+    print(name, n, scheme, "H0 %.6e/%.6e H1 %.6e/%.6e dH gpu %.4e oracle %.4e  dq %.2e dp %.2e du %.2e" % (
         g_h0, h0, g_h1, h1, g_h1 - g_h0, h1 - h0, e_q, e_p, e_u))
     assert abs(g_h0 - h0) < 1e-6 * abs(h0)
     assert abs(g_h1 - h1) < 1e-6 * abs(h1)

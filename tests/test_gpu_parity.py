@@ -214,3 +214,58 @@ def test_cic_methods_bit_identical(rsd):
     p.set_cic_method("sorted")
     assert torch.equal(r1, r2)
     assert torch.equal(l1, l2)
+
+
+@pytest.mark.parametrize("case", [("c0fd", None), ("c2", 32), ("c2", 96)], ids=_ids)
+def test_wiener_start_matches_oracle(case):
+    """The Wiener-filter starting point (fzw_wiener_start) against the
+    oracle's, element by element (relative 1e-5 normwise), on one chain and on
+    a plan of two meshes."""
+    from oracle import wiener
+    name, n = case
+    w, m, nu_t, nu_e, counts = mock_case(name, n)
+    p = plan_for(w)
+    p.set_counts(0, dev_counts(counts))
+    got = host(p.wiener_start()).reshape(counts.shape)
+    ref = wiener.wiener_white_noise(m, counts)
+    err = relnorm(got, ref)
+    print(name, n, "wiener start err %.2e, |nu| rms %.3f" % (err, float(np.sqrt(np.mean(ref ** 2)))))
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("case", [("c2", 64), ("c1", None)], ids=_ids)
+def test_validation_statistics_match_oracle(case):
+    """Power-spectrum monopole and quadrupole (redshift-space density), cross
+    spectrum with the linear density, and the reduced bispectrum at
+    k1 = 0.1, k2 = 0.2 h/Mpc, through the C ABI against the oracle's
+    statistics of the same FP32 fields.  Mode counts and triangle counts are
+    exact; spectra within 1e-5 relative; bispectra within 1e-4 of their
+    largest magnitude."""
+    from oracle import stats
+    name, n = case
+    w, m, nu, counts, p, bias = _gpu_forward(name, n, "near")
+    st = m.forward(nu, w.chains[0].bias, counts)
+    ch = w.chains[0]
+    delta = (st["rho"] - 1.0).astype(np.float32)
+    dl = st["dl"].astype(np.float32)
+    kf = 2 * np.pi / ch.box
+    nb = 12
+    gp = host(p.power_multipoles(dev(delta.ravel()), None, k_lo=kf, dk=2 * kf, nbins=nb, mesh_n=ch.n))
+    km, cnt, p0, p2 = stats.multipoles(delta.astype(np.float64), None, ch.box, kf, 2 * kf, nb)
+    assert np.array_equal(gp[:, 1], cnt)
+    assert np.allclose(gp[:, 0], km, rtol=1e-12)
+    assert np.allclose(gp[:, 2], p0, rtol=1e-5)
+    assert np.all(np.abs(gp[:, 3] - p2) < 1e-5 * np.abs(p0))
+    gx = host(p.power_multipoles(dev(delta.ravel()), dev(dl.ravel()), k_lo=kf, dk=2 * kf, nbins=nb, mesh_n=ch.n))
+    _, _, x0, x2 = stats.multipoles(delta.astype(np.float64), dl.astype(np.float64), ch.box, kf, 2 * kf, nb)
+    assert np.allclose(gx[:, 2], x0, rtol=1e-5, atol=1e-5 * np.abs(x0).max())
+    thetas = np.linspace(0.05, np.pi - 0.05, 9)
+    gb = host(p.bispectrum(dev(delta.ravel()), 0.1, 0.2, 2 * kf, thetas, mesh_n=ch.n))
+    k3, b, q, tri = stats.bispectrum(delta.astype(np.float64), ch.box, 0.1, 0.2, 2 * kf, thetas)
+    print(name, n, "P0 err %.2e  B max err %.2e (max |B| %.3e)  Q" % (
+        float(np.max(np.abs(gp[:, 2] / p0 - 1))), float(np.max(np.abs(gb[:, 1] - b))), float(np.abs(b).max())),
+        np.round(gb[:, 2], 4), np.round(q, 4))
+    assert np.allclose(gb[:, 0], k3, rtol=1e-12)
+    assert np.allclose(gb[:, 3], tri, rtol=1e-5)
+    assert np.all(np.abs(gb[:, 1] - b) < 1e-4 * np.abs(b).max())
+    assert np.all(np.abs(gb[:, 2] - q) < 1e-4 * np.abs(q).max())
