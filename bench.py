@@ -156,12 +156,15 @@ def _trajectory(w, steps, reps, torch, Plan, CosmoParams, WebParams, step_size=1
     return ms
 
 
-def _nuts_leg(w, md, reps, torch, Plan, CosmoParams, WebParams, step_size=1e-5):
+def _nuts_leg(w, md, reps, torch, Plan, CosmoParams, WebParams, step_size=1e-7):
     """Time no-U-turn transitions of every chain of workload w at a step so
-    small that no trajectory turns, so every transition builds the full tree
-    of 2^md - 1 leaves: the cost per leaf, next to a plain leapfrog step,
-    is the tree's bookkeeping overhead (checkpoints, U-turn dot products,
-    candidate copies, per-doubling host checks)."""
+    small that no trajectory turns or diverges (the timing state sits far
+    from the synthetic counts, where gradients are large; the free
+    parameters get a tiny inverse mass for the same reason), so every
+    transition builds the full tree of 2^md - 1 leaves: the cost per leaf,
+    next to a plain leapfrog step, is the tree's bookkeeping overhead
+    (checkpoints, U-turn dot products, candidate copies, per-doubling host
+    checks)."""
     import numpy as np
     import fzw_inputs as fi
     from paper_2506_03969_amd import nuts_n_uniforms
@@ -175,7 +178,7 @@ def _nuts_leg(w, md, reps, torch, Plan, CosmoParams, WebParams, step_size=1e-5):
     u = torch.from_numpy(np.stack([fi.free_start(w, ch) for ch in w.chains]).astype(np.float32)).cuda()
     base = torch.from_numpy(np.stack([ch.bias for ch in w.chains]).astype(np.float32)).cuda()
     minv = torch.ones_like(nu)
-    minv_u = torch.full_like(u, 1e-2)
+    minv_u = torch.full_like(u, 1e-6)
     step = torch.full((len(w.chains),), step_size, dtype=torch.float32, device="cuda")
     gen = torch.Generator(device="cuda")
     gen.manual_seed(11)
