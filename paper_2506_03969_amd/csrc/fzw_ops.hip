@@ -846,6 +846,87 @@ __global__ __launch_bounds__(256) void likelihood_kernel(LikeArgs a) {
   }
 }
 
+// f(x) = x/(1+x) - log1p(x): the part of d lnP/d beta that cancels to
+// -x^2/2 for small x = nbar/beta; its alternating series below 0.1
+// (truncated after x^9, relative error < 2e-8), the direct form above
+// (relative error ~1e-6 at x = 0.1, smaller beyond).
+__device__ __forceinline__ float nb_cancel(float x) {
+  if (x < 0.1f) {
+    const float p = -1.f / 2 + x * (2.f / 3 + x * (-3.f / 4 + x * (4.f / 5 + x * (-5.f / 6 + x * (6.f / 7 +
+                    x * (-7.f / 8 + x * (8.f / 9)))))));
+    return x * x * p;
+  }
+  return x / (1.f + x) - log1pf(x);
+}
+
+// The likelihood pass in float32 arithmetic per voxel with float64 sums, the
+// cancelling terms rewritten so that no digits are lost:
+//   d lnP/d beta = [psi(n+beta) - psi(beta) - n/(beta+nbar)] + f(nbar/beta)
+// (the same quantity as psi(n+beta) - psi(beta) - ln(1 + nbar/beta) +
+// (nbar - n)/(beta + nbar), with the part that cancels to -x^2/2 for small
+// x = nbar/beta evaluated by f), lnGamma(n+beta) - lnGamma(beta) as
+// logarithms of 8-term products, and n ln(nbar/beta) from the float64
+// ln nbar.  Counts above 64 take the float64 special functions.
+__global__ __launch_bounds__(256) void likelihood32_kernel(LikeArgs a) {
+  __shared__ double red[4];
+  const long long c = blockIdx.y;
+  const long long nv = a.nv;
+  const double lnc = a.scal[c * kScalStride + kScalLnC];
+  const bool grad = a.ghat != nullptr;
+  double sl = 0.0, sg = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x) {
+    const float lf = a.logf[c * nv + i];
+    const float beta = a.beta[c * nv + i];
+    const int n = a.counts[c * nv + i];
+    const float fn = (float)n;
+    const double lnb = lnc + (double)lf;
+    const float nb = expf((float)lnb);
+    const float x = nb / beta;
+    const float l1p = log1pf(x);
+    const float ib = 1.f / (beta + nb);
+    // lnGamma(n+beta) - lnGamma(beta) and psi(n+beta) - psi(beta) as sums over
+    // m < n of ln(beta+m) and 1/(beta+m): per 8 terms one logarithm of their
+    // product and one division of the product's derivative by it
+    float lg = 0.f, sr = 0.f;
+    double dbig = 0.0;
+    if (n <= 64) {
+      for (int m0 = 0; m0 < n; m0 += 8) {
+        float pq = 0.f, qq = 1.f;
+        const int m1 = min(n, m0 + 8);
+        for (int m = m0; m < m1; ++m) {
+          const float bm = beta + (float)m;
+          pq = fmaf(pq, bm, qq);
+          qq *= bm;
+        }
+        lg += ::logf(qq);
+        if (grad) sr += pq / qq;
+      }
+    } else {
+      lg = (float)nb_lgamma_big_d(n, (double)beta);
+      if (grad)
+        dbig = nb_digamma_big(n, (double)beta) - (double)l1p + ((double)nb - (double)n) / ((double)beta + (double)nb);
+    }
+    sl += (double)lg - (double)(beta + fn) * (double)l1p + (double)n * (lnb - (double)::logf(beta));
+    const float gh = beta * (fn - nb) * ib;
+    sg += (double)gh;
+    if (a.nbar) a.nbar[c * nv + i] = nb;
+    if (grad) {
+      a.ghat[c * nv + i] = gh;
+      a.nbv[c * nv + i] = nb;
+      // psi(n+beta) - psi(beta) - n/(beta+nbar) + f(nbar/beta): the first two
+      // terms are of one size with no more cancellation than ~m/beta; f is
+      // the small-x-cancelling part
+      a.dbeta[c * nv + i] = n <= 64 ? (sr - fn * ib) + nb_cancel(x) : (float)dbig;
+    }
+  }
+  const double s1 = block_sum(sl, red);
+  const double s2 = block_sum(sg, red);
+  if (threadIdx.x == 0) {
+    a.partial[(c * gridDim.x + blockIdx.x) * 2 + 0] = s1;
+    a.partial[(c * gridDim.x + blockIdx.x) * 2 + 1] = s2;
+  }
+}
+
 // Per-voxel adjoint of bias, memberships and web tensors.  The bias-table
 // gradient sum_i p_r,i dtheta_c,i is reduced through LDS: every pass of the
 // block stores p (float) and dtheta (float64) of its 256 voxels, then thread t
@@ -1009,8 +1090,9 @@ void launch_voxel_bwd(int w, const VoxelArgs& a, int chains, int nblk, hipStream
   if (w == 1) hipLaunchKernelGGL(voxel_bwd_kernel<1>, g, dim3(256), 0, s, a);
   else hipLaunchKernelGGL(voxel_bwd_kernel<2>, g, dim3(256), 0, s, a);
 }
-void launch_likelihood(const LikeArgs& a, int chains, int nblk, hipStream_t s) {
-  hipLaunchKernelGGL(likelihood_kernel, dim3(nblk, chains), dim3(256), 0, s, a);
+void launch_likelihood(const LikeArgs& a, int chains, int nblk, bool fp64, hipStream_t s) {
+  if (fp64) hipLaunchKernelGGL(likelihood_kernel, dim3(nblk, chains), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(likelihood32_kernel, dim3(nblk, chains), dim3(256), 0, s, a);
 }
 void launch_finalize(const FinalArgs& a, int chains, hipStream_t s) {
   if (a.mode == 2) hipLaunchKernelGGL(finalize_table_kernel, dim3(a.ne, chains), dim3(256), 0, s, a);

@@ -213,7 +213,7 @@ void launch_cic_adjoint(const CicArgs& a, int chains, hipStream_t s);
 void launch_cic_deposit_atomic(const CicArgs& a, int chains, hipStream_t s);
 void launch_voxel_fwd(int w, const VoxelArgs& a, int chains, int nblk, hipStream_t s);
 void launch_voxel_bwd(int w, const VoxelArgs& a, int chains, int nblk, hipStream_t s);
-void launch_likelihood(const LikeArgs& a, int chains, int nblk, hipStream_t s);
+void launch_likelihood(const LikeArgs& a, int chains, int nblk, bool fp64, hipStream_t s);
 void launch_finalize(const FinalArgs& a, int chains, hipStream_t s);
 void launch_count_consts(const uint16_t* cnt, long long nv, double* partial, int nblk, double* scal, hipStream_t s);
 void launch_kick(const LeapArgs& a, int chains, float frac, hipStream_t s);

@@ -175,6 +175,9 @@ struct fzw_plan {
   int* nuts_any_host = nullptr;       // pinned
   double* stats_buf = nullptr;        // partials and scalars of the validation statistics
   int integrator = FZW_INT_LEAPFROG;  // splitting scheme of fzw_leapfrog
+  // likelihood pass in float64 per voxel instead of compensated float32
+  // (FZW_LIKELIHOOD_FP64=1; both sum in float64)
+  bool like_fp64 = false;
 };
 
 namespace {
@@ -641,7 +644,7 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     la.nv = g.nv;
     {
       Timed tm(p, FZW_K_LIKE, (2.5 + (nbar ? 1 : 0)) * field_bytes(g));
-      launch_likelihood(la, g.nc, g.nblk, s);
+      launch_likelihood(la, g.nc, g.nblk, p->like_fp64, s);
     }
     fa.mode = 1;
     fa.logl = logl ? logl + g.c0 : nullptr;
@@ -1096,6 +1099,10 @@ fzw_status fzw_plan_create(fzw_plan** out, int n_chains, const int* mesh_n, cons
   }
   *out = nullptr;
   auto* p = new fzw_plan();
+  {
+    const char* e = std::getenv("FZW_LIKELIHOOD_FP64");
+    p->like_fp64 = e && e[0] == '1';
+  }
   fzw_status st = guarded([&] {
     if (web->n_webs < 1 || web->n_webs > 2) throw Error(FZW_E_ARG, "n_webs must be 1 or 2");
     if (cosmo->rsd_axis < -1 || cosmo->rsd_axis > FZW_RSD_RADIAL)
