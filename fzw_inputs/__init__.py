@@ -146,6 +146,12 @@ def _four_class_free():
     return [((r,), COL_ALPHA) for r in range(4)]
 
 
+def full_table_free(n_regions: int):
+    """Every entry of the table free: the 16-region model's 64 parameters
+    (alpha, eps, rho_th and beta of every region)."""
+    return [((r,), col) for r in range(n_regions) for col in range(4)]
+
+
 def _sixteen_free():
     out = []
     for j in range(4):
@@ -268,19 +274,30 @@ def tie_array(w: Workload) -> np.ndarray:
 
 
 def prior_arrays(w: Workload):
-    """Gaussian prior (mean, sigma) on the log of every free bias parameter."""
+    """Gaussian prior (mean, sigma) on the log of the magnitude of every free
+    bias parameter: the alpha and beta priors of the paper's tests; eps and
+    rho_th (free only in the full table) centred on the first chain's table
+    with width 0.3."""
     mu, sig = [], []
     for regions, col in w.free:
         if col == COL_BETA:
             mu.append(PRIOR_MU_BETA), sig.append(PRIOR_SIGMA_BETA)
-        else:
+        elif col == COL_ALPHA:
             mu.append(PRIOR_MU_ALPHA), sig.append(PRIOR_SIGMA_ALPHA)
+        else:
+            mu.append(float(np.log(abs(w.chains[0].bias[regions[0], col])))), sig.append(0.3)
     return np.array(mu), np.array(sig)
 
 
 def free_start(w: Workload, chain: Chain) -> np.ndarray:
-    """Log of the free bias parameters of a chain (the sampled coordinates)."""
-    return np.log(np.array([chain.bias[r[0], c] for r, c in w.free]))
+    """Log of the magnitude of the free bias parameters of a chain (the
+    sampled coordinates)."""
+    return np.log(np.abs(np.array([chain.bias[r[0], c] for r, c in w.free])))
+
+
+def free_signs(w: Workload, chain: Chain) -> np.ndarray:
+    """Sign of every free bias parameter in a chain's table (+1 or -1)."""
+    return np.where(np.array([chain.bias[r[0], c] for r, c in w.free]) < 0, -1, 1).astype(np.int64)
 
 
 def bytes_model(n: int, n_webs: int, leapfrog: bool = False) -> float:

@@ -125,11 +125,20 @@ fzw_status fzw_value_and_grad(fzw_plan* plan, const float* nu, const float* bias
 
 /* Free bias parameters for HMC: n_free parameters shared by all chains.
  * tie (host, int [R*4]) maps each table entry to a free-parameter index or -1
- * (entry stays at its base value); a free parameter is sampled as u = ln b.
+ * (entry stays at its base value); a free parameter is sampled as u = ln b
+ * (u = ln |b| with fzw_set_sampling_signs).
  * prior_mu, prior_sigma (host, double [n_free]) are the log-normal
  * hyper-parameters (Eq. 'lognormal').  n_free <= 64. */
 fzw_status fzw_set_sampling(fzw_plan* plan, const int* tie, int n_free, const double* prior_mu,
                             const double* prior_sigma);
+
+/* Signs of the free parameters (host, int [n_free], each +1 or -1; n_free as
+ * given to fzw_set_sampling, which resets every sign to +1): a free parameter
+ * is sign * exp(u), so a signed entry such as a negative exponential-cut-off
+ * exponent (the low-density cut-off of Eq. 'local_bias') can be sampled with a
+ * log-normal prior on its magnitude.  Used for the full 64-parameter table of
+ * the 16-region model. */
+fzw_status fzw_set_sampling_signs(fzw_plan* plan, const int* sign, int n_free);
 
 /* One kick-drift-kick leapfrog trajectory of n_steps steps per chain, on the
  * potential U = -logL + |nu|^2/2 + sum_f (u_f - mu_f)^2/(2 sigma_f^2), with a

@@ -15,18 +15,21 @@ from __future__ import annotations
 import numpy as np
 
 
-def tied_table(base, u, tying):
-    """Bias table with every entry listed for free parameter f set to exp(u_f).
+def tied_table(base, u, tying, signs=None):
+    """Bias table with every entry listed for free parameter f set to
+    s_f exp(u_f) (s_f = +1 unless `signs` is given: a signed parameter such as
+    a negative cut-off exponent is sampled through the log of its magnitude).
     `tying` is a list of (region tuple, column) per free parameter."""
     t = np.array(base, dtype=np.float64, copy=True)
     for fi, (regions, col) in enumerate(tying):
+        s = 1.0 if signs is None else float(signs[fi])
         for r in regions:
-            t[r, col] = np.exp(u[fi])
+            t[r, col] = s * np.exp(u[fi])
     return t
 
 
-def potential_and_grad(model, nu, u, base, tying, mu, sigma, counts):
-    table = tied_table(base, u, tying)
+def potential_and_grad(model, nu, u, base, tying, mu, sigma, counts, signs=None):
+    table = tied_table(base, u, tying, signs)
     logl, dnu, dtab = model.value_and_grad(nu, table, counts)
     uu = np.asarray(u, dtype=np.float64)
     mu = np.asarray(mu, dtype=np.float64)
@@ -35,7 +38,8 @@ def potential_and_grad(model, nu, u, base, tying, mu, sigma, counts):
     gnu = -dnu + nu
     gu = np.zeros_like(uu)
     for fi, (regions, col) in enumerate(tying):
-        gu[fi] = -sum(dtab[r, col] for r in regions) * np.exp(uu[fi])
+        s = 1.0 if signs is None else float(signs[fi])
+        gu[fi] = -sum(dtab[r, col] for r in regions) * s * np.exp(uu[fi])
     gu += (uu - mu) / sigma ** 2
     return pot, gnu, gu
 

@@ -1171,7 +1171,7 @@ void launch_energy(const LeapArgs& a, int chains, int nblk, hipStream_t s) {
 }
 
 // Free bias parameters: one workgroup per chain.
-//   mode 0: table = base with tied entries exp(u)
+//   mode 0: table = base with tied entries sign * exp(u)
 //   mode 1: half kick of p_u with frac * step
 //   mode 2: drift of u with frac * step
 //   mode 3: Hamiltonian: H = -logL + field energy partials + prior + kinetic(u)
@@ -1184,7 +1184,7 @@ __global__ void params_kernel(ParamArgs a, int mode, float frac, int nblk_energy
   if (mode == 0) {
     for (int e = threadIdx.x; e < ne; e += blockDim.x) {
       const int f = a.tie[e];
-      a.table[c * ne + e] = f >= 0 ? expf(u[f]) : a.base[c * ne + e];
+      a.table[c * ne + e] = f >= 0 ? a.sign[f] * expf(u[f]) : a.base[c * ne + e];
     }
   } else if (mode == 1) {
     const float e = a.step[c] * frac;

@@ -116,6 +116,7 @@ struct ParamArgs {
   const double* mu;
   const double* sigma;
   const int* tie;
+  const float* sign;        // [n_free] +1 or -1: a free parameter is sign * exp(u)
   const float* base;
   float* table;
   const float* dtable;

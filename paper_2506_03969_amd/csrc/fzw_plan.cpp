@@ -143,6 +143,7 @@ struct fzw_plan {
   float* dtable_tmp = nullptr;
   double* epartial = nullptr;         // leapfrog energy partials [n_chains][kEBlk]
   int* tie = nullptr;
+  float* fsign = nullptr;             // sign of every free parameter (+1 unless set)
   double* mu = nullptr;
   double* sigma = nullptr;
   int nfree = -1;
@@ -1033,6 +1034,7 @@ void run_nuts(fzw_plan* p, float* nu, float* u, const float* z_nu, const float* 
   pa.mu = p->mu;
   pa.sigma = p->sigma;
   pa.tie = p->tie;
+  pa.sign = p->fsign;
   pa.base = base;
   pa.table = p->table_tmp;
   pa.dtable = p->dtable_tmp;
@@ -1167,6 +1169,7 @@ fzw_status fzw_plan_create(fzw_plan** out, int n_chains, const int* mesh_n, cons
     p->dtable_tmp = dalloc<float>(p, (size_t)n_chains * p->R * 4);
     p->epartial = dalloc<double>(p, (size_t)n_chains * kEBlk);
     p->tie = dalloc<int>(p, (size_t)p->R * 4);
+    p->fsign = dalloc<float>(p, 64);
     p->mu = dalloc<double>(p, 64);
     p->sigma = dalloc<double>(p, 64);
     // default priority, non-blocking: the caller's stream may be the legacy
@@ -1250,6 +1253,10 @@ fzw_status fzw_set_sampling(fzw_plan* p, const int* tie, int n_free, const doubl
       HIPCHK(hipMemcpy(p->mu, prior_mu, sizeof(double) * n_free, hipMemcpyHostToDevice));
       HIPCHK(hipMemcpy(p->sigma, prior_sigma, sizeof(double) * n_free, hipMemcpyHostToDevice));
     }
+    {
+      std::vector<float> ones(64, 1.f);
+      HIPCHK(hipMemcpy(p->fsign, ones.data(), sizeof(float) * 64, hipMemcpyHostToDevice));
+    }
     p->nfree = n_free;
     for (auto& kv : p->graphs) {
       (void)hipGraphExecDestroy(kv.second.e);
@@ -1291,6 +1298,7 @@ static void enqueue_trajectory(fzw_plan* p, float* nu, float* u, float* p_nu, fl
   pa.mu = p->mu;
   pa.sigma = p->sigma;
   pa.tie = p->tie;
+  pa.sign = p->fsign;
   pa.base = base;
   pa.table = p->table_tmp;
   pa.dtable = p->dtable_tmp;
@@ -1569,6 +1577,22 @@ fzw_status fzw_wiener_start(fzw_plan* p, float* nu) {
       zi(g, &g.spec[0], io, 1, s);
     }
     HIPCHK(hipGetLastError());
+  });
+}
+
+fzw_status fzw_set_sampling_signs(fzw_plan* p, const int* sign, int n_free) {
+  if (!p || !sign || n_free < 0 || n_free > 64) {
+    g_last_error = "fzw_set_sampling_signs: bad argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    if (n_free != p->nfree) throw Error(FZW_E_STATE, "n_free differs from the one given to fzw_set_sampling");
+    std::vector<float> sg(64, 1.f);
+    for (int f = 0; f < n_free; ++f) {
+      if (sign[f] != 1 && sign[f] != -1) throw Error(FZW_E_ARG, "signs must be +1 or -1");
+      sg[f] = (float)sign[f];
+    }
+    HIPCHK(hipMemcpy(p->fsign, sg.data(), sizeof(float) * 64, hipMemcpyHostToDevice));
   });
 }
 

@@ -98,6 +98,7 @@ def load_library(path: str = _LIB_PATH):
     lib.fzw_welford.argtypes = [vp, vp, vp, vp, ll, i]
     lib.fzw_wiener_start.argtypes = [vp, vp]
     lib.fzw_set_integrator.argtypes = [vp, i]
+    lib.fzw_set_sampling_signs.argtypes = [vp, ctypes.POINTER(i), i]
     lib.fzw_power_multipoles.argtypes = [vp, i, vp, vp, d, d, i, vp]
     lib.fzw_bispectrum.argtypes = [vp, i, vp, d, d, d, i, ctypes.POINTER(d), vp]
     lib.fzw_inverse_mass.argtypes = [vp, vp, vp, ll, i]
@@ -110,7 +111,7 @@ def load_library(path: str = _LIB_PATH):
     for name in ("fzw_plan_create", "fzw_set_counts", "fzw_forward", "fzw_value_and_grad",
                  "fzw_set_sampling", "fzw_leapfrog", "fzw_get_field", "fzw_fft_r2c", "fzw_fft_c2r",
                  "fzw_nuts", "fzw_welford", "fzw_inverse_mass", "fzw_wiener_start", "fzw_power_multipoles",
-                 "fzw_bispectrum", "fzw_set_integrator"):
+                 "fzw_bispectrum", "fzw_set_integrator", "fzw_set_sampling_signs"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -244,6 +245,11 @@ class Plan:
         arr_s = (ctypes.c_double * max(nf, 1))(*[float(x) for x in sigma])
         _check(_lib.fzw_set_sampling(self._h, arr_t, nf, arr_m, arr_s), "fzw_set_sampling")
         self.nfree = nf
+
+    def set_sampling_signs(self, signs: Sequence[int]):
+        """Free parameter f is signs[f] * exp(u_f) (after set_sampling)."""
+        arr = (ctypes.c_int * max(len(signs), 1))(*[int(x) for x in signs])
+        _check(_lib.fzw_set_sampling_signs(self._h, arr, len(signs)), "fzw_set_sampling_signs")
 
     def leapfrog(self, nu, u, p_nu, p_u, bias_base, minv_nu, minv_u, step, n_steps, h_start=None, h_end=None):
         if h_start is None:

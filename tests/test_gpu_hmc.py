@@ -107,3 +107,38 @@ def test_graph_replay_matches_first_launch():
     for r in results[1:]:
         for a, b in zip(results[0], r):
             assert torch.equal(a, b)
+
+
+def test_leapfrog_full_signed_table_matches_oracle():
+    """All 64 entries of the 16-region table free (negative cut-off exponents
+    as -exp(u), fzw_set_sampling_signs): a trajectory against the oracle's."""
+    import dataclasses
+    w, m, nu_t, nu_e, counts = mock_case("c2", 32)
+    ch = w.chains[0]
+    wf = dataclasses.replace(w, free=fi.full_table_free(w.n_regions))
+    mu, sig = fi.prior_arrays(wf)
+    u0 = fi.free_start(wf, ch)
+    signs = fi.free_signs(wf, ch)
+    nu = fi.near_truth_noise(ch)
+    g = fi.rng_for(ch, fi.ROLE_MOMENTUM)
+    p_nu = g.standard_normal(nu.shape)
+    p_u = g.standard_normal(u0.shape)
+    eps, steps = 2e-3, 4
+    minv_u = np.full(u0.shape, 1e-3)
+    gfn = lambda q, u: hmc.potential_and_grad(m, q, u, ch.bias, wf.free, mu, sig, counts, signs)
+    q1, u1, p1, pu1, h0, h1 = hmc.leapfrog(gfn, nu, u0, p_nu, p_u, 1.0, minv_u, eps, steps)
+    plan = plan_for(wf)
+    plan.set_counts(0, dev_counts(counts))
+    plan.set_sampling(fi.tie_array(wf), mu, sig)
+    plan.set_sampling_signs(signs)
+    t_nu, t_u = dev(nu.ravel()), dev(u0[None])
+    t_p, t_pu = dev(p_nu.ravel()), dev(p_u[None])
+    hs, he = plan.leapfrog(t_nu, t_u, t_p, t_pu, dev(ch.bias[None]), torch.ones_like(t_nu), dev(minv_u[None]),
+                           dev(np.array([eps])), steps)
+    g_h0, g_h1 = float(host(hs)[0]), float(host(he)[0])
+    e_q = relnorm(host(t_nu).reshape(nu.shape) - nu, q1 - nu)
+    e_u = float(np.max(np.abs(host(t_u)[0] - u1)))
+    print("64 free: H0 %.6e/%.6e H1 %.6e/%.6e dq %.2e du %.2e" % (g_h0, h0, g_h1, h1, e_q, e_u))
+    assert abs(g_h0 - h0) < 1e-6 * abs(h0)
+    assert abs(g_h1 - h1) < 1e-6 * abs(h1)
+    assert e_q < 1e-4 and e_u < 1e-5

@@ -135,3 +135,25 @@ def test_blanes_scheme_beats_leapfrog_on_a_gaussian_at_equal_cost():
         *_, h0, h1 = hmc.integrate(gfn, q0, np.zeros(1), p, np.zeros(1), 1.0, 0.0, 2 * eps, 20, "blanes2")
         e_b2.append(abs(h1 - h0))
     assert np.mean(e_b2) < 0.5 * np.mean(e_lf)
+
+
+def test_potential_gradient_with_the_full_signed_table():
+    """All 64 entries of the 16-region table free, the negative cut-off
+    exponents sampled as -exp(u): dU/du by central differences."""
+    import dataclasses
+    w, m, nu_t, nu_e, counts = mock_case("c2", 16)
+    ch = w.chains[0]
+    wf = dataclasses.replace(w, free=fi.full_table_free(w.n_regions))
+    mu, sig = fi.prior_arrays(wf)
+    u = fi.free_start(wf, ch)
+    signs = fi.free_signs(wf, ch)
+    assert np.any(signs < 0) and len(u) == 64
+    assert np.allclose(hmc.tied_table(ch.bias, u, wf.free, signs), ch.bias)
+    gfn = lambda q, uu: hmc.potential_and_grad(m, q, uu, ch.bias, wf.free, mu, sig, counts, signs)
+    pot, gnu, gu = gfn(nu_t, u)
+    rng = np.random.default_rng(3)
+    for i in rng.choice(64, size=10, replace=False):
+        e = np.zeros_like(u)
+        e[i] = 1e-6
+        fd = (gfn(nu_t, u + e)[0] - gfn(nu_t, u - e)[0]) / 2e-6
+        assert fd == pytest.approx(gu[i], rel=1e-5, abs=1e-6 * np.abs(gu).max())
