@@ -163,6 +163,8 @@ fzw_status fzw_leapfrog(fzw_plan* plan, float* nu, float* u, float* p_nu, float*
  * the leaves with weights exp(-H) (uniformly within a subtree, with
  * probability min(1, W_subtree / W_tree) when the subtree is joined).
  * All chains advance in lock step; a chain whose trajectory has ended idles.
+ * Each leaf is one step of the plan's splitting scheme (fzw_set_integrator;
+ * kick-drift-kick by default).
  * All arrays are device memory:
  *   nu, u              float32 state (packed chains; [n_chains][n_free]),
  *                      replaced by the new state
@@ -259,8 +261,8 @@ fzw_status fzw_bispectrum(fzw_plan* plan, int mesh_n, const float* delta, double
  *   FZW_INT_BLANES2   a = (0.21178, 0.57644, 0.21178), b = (1/2, 1/2): two
  *   FZW_INT_YOSHIDA4  three leapfrog steps of w1, w0, w1 eps with
  *                     w1 = 1/(2 - 2^(1/3)), w0 = 1 - 2 w1 (fourth order): three
- * Applies to later fzw_leapfrog calls (each scheme has its own graph);
- * fzw_nuts always uses leapfrog leaves. */
+ * Applies to later fzw_leapfrog calls (each scheme has its own graph) and
+ * to the leaves of fzw_nuts (one step of the scheme per leaf). */
 enum { FZW_INT_LEAPFROG = 0, FZW_INT_BLANES2 = 1, FZW_INT_YOSHIDA4 = 2 };
 fzw_status fzw_set_integrator(fzw_plan* plan, int kind);
 

@@ -37,6 +37,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
+from .hmc import SCHEMES
+
 DELTA_MAX = 1000.0
 
 
@@ -82,10 +84,13 @@ class Transition:
     margin_turn: float = math.inf
 
 
-def transition(pot_grad, q0, z, minv, eps, uniforms, max_depth, start=None):
+def transition(pot_grad, q0, z, minv, eps, uniforms, max_depth, start=None, scheme="leapfrog"):
     """One NUTS transition from q0.  `pot_grad(q) -> (U, dU/dq)` on flat float64
     vectors; minv is the diagonal inverse mass matrix; `start` optionally holds
-    (U, dU/dq) at q0."""
+    (U, dU/dq) at q0.  Each leaf is one step of a splitting scheme of
+    oracle.hmc.SCHEMES (a symmetric, volume-preserving step, so the tree
+    stays a valid NUTS trajectory)."""
+    kicks, drifts = SCHEMES[scheme]
     q0 = np.asarray(q0, dtype=np.float64)
     minv = np.broadcast_to(np.asarray(minv, dtype=np.float64), q0.shape)
     u0, g0 = start if start is not None else pot_grad(q0)
@@ -104,10 +109,11 @@ def transition(pot_grad, q0, z, minv, eps, uniforms, max_depth, start=None):
         cand_s = None
         stop = False
         for k in range(1 << j):
-            p = p - 0.5 * v * eps * g
-            q = q + v * eps * minv * p
-            u_pot, g = pot_grad(q)
-            p = p - 0.5 * v * eps * g
+            for a_i, b_i in zip(kicks, drifts):
+                p = p - a_i * v * eps * g
+                q = q + b_i * v * eps * minv * p
+                u_pot, g = pot_grad(q)
+            p = p - kicks[-1] * v * eps * g
             h = u_pot + 0.5 * float(np.sum(minv * p * p))
             n_leaf += 1
             acc_sum += min(1.0, math.exp(min(0.0, h0 - h)))

@@ -5,7 +5,8 @@
 // a zero step.  State vectors hold the field part of every chain (packed like
 // nu) followed by the free parameters ([chains][n_free]).
 //
-// Per leaf: kick, drift, gradient, kick, energy partials, one scalar kernel
+// Per leaf: one step of the plan's splitting scheme (kick, drift, gradient,
+// ..., kick; kick-drift-kick by default), energy partials, one scalar kernel
 // per chain (divergence, multinomial weight, progressive candidate choice),
 // then one pass that adds the leaf to the subtree's momentum sum, copies the
 // candidate, writes the block-start checkpoints and forms the dot products of
@@ -42,7 +43,7 @@ __device__ __forceinline__ void put_partials(const NutsVec& a, long long c, int 
   }
 }
 
-__global__ void __launch_bounds__(kNutsThreads) nuts_vec_kernel(NutsVec a, NutsSeg g, int op) {
+__global__ void __launch_bounds__(kNutsThreads) nuts_vec_kernel(NutsVec a, NutsSeg g, int op, float frac) {
   __shared__ double red[kNutsThreads / 64];
   const long long c = g.c0 + blockIdx.y;
   const NutsChain& st = a.st[c];
@@ -52,7 +53,7 @@ __global__ void __launch_bounds__(kNutsThreads) nuts_vec_kernel(NutsVec a, NutsS
   const long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   const int slot = g.is_u ? kNutsBlk : (int)blockIdx.x;
   if (op == kNutsOpKick) {
-    const float e = 0.5f * st.se;
+    const float e = frac * st.se;
     if (e == 0.f) return;
     for (long long i = i0; i < g.len; i += stride) {
       const long long x = base + i;
@@ -60,7 +61,7 @@ __global__ void __launch_bounds__(kNutsThreads) nuts_vec_kernel(NutsVec a, NutsS
       a.wp[x] -= e * gr;
     }
   } else if (op == kNutsOpDrift) {
-    const float e = st.se;
+    const float e = frac * st.se;
     if (e == 0.f) return;
     for (long long i = i0; i < g.len; i += stride) {
       const long long x = base + i;
@@ -333,11 +334,11 @@ unsigned blocks_for(long long n, unsigned cap) {
 
 }  // namespace
 
-void launch_nuts_vec(const NutsVec& a, const NutsSeg& g, int op, hipStream_t s) {
+void launch_nuts_vec(const NutsVec& a, const NutsSeg& g, int op, float frac, hipStream_t s) {
   // the field part always runs kNutsBlk blocks per chain, so that every
   // partial slot is written; the parameter part one block per chain
   const unsigned bx = g.is_u ? 1u : (unsigned)kNutsBlk;
-  hipLaunchKernelGGL(nuts_vec_kernel, dim3(bx, g.nc), dim3(kNutsThreads), 0, s, a, g, op);
+  hipLaunchKernelGGL(nuts_vec_kernel, dim3(bx, g.nc), dim3(kNutsThreads), 0, s, a, g, op, frac);
 }
 
 template <int NCHK>

@@ -185,7 +185,8 @@ struct NutsLeafPlan {
   int slot[12];     // their checkpoint slots (max_depth <= 12)
 };
 
-void launch_nuts_vec(const NutsVec& a, const NutsSeg& g, int op, hipStream_t s);
+// frac scales the chain's signed step for the kick and drift ops
+void launch_nuts_vec(const NutsVec& a, const NutsSeg& g, int op, float frac, hipStream_t s);
 void launch_nuts_leaf(const NutsVec& a, const NutsSeg& g, const NutsLeafPlan& lp, hipStream_t s);
 void launch_nuts_ugrad(const NutsVec& a, const ParamArgs& pa, long long uoff, int chains, hipStream_t s);
 struct NutsScalarArgs {

@@ -946,6 +946,27 @@ void free_plan(fzw_plan* p) {
 
 }  // namespace
 
+// Splitting schemes of one integration step, K(a_0) D(b_1) K(a_1) ... D(b_m)
+// K(a_m), the gradient evaluated after every drift (Section 2.2 names
+// second- and fourth-order HMC and the variant of Blanes, Casas & Sanz-Serna
+// 2014): kick-drift-kick; the two-stage splitting with b = 0.21178; three
+// leapfrog steps of w1, w0, w1 with w1 = 1/(2 - 2^(1/3)), w0 = 1 - 2 w1
+// (Yoshida 1990), adjacent kicks merged.
+struct Scheme {
+  int stages;
+  double kick[4];
+  double drift[3];
+};
+
+static const Scheme& scheme_of(int kind) {
+  static const Scheme lf = {1, {0.5, 0.5}, {1.0}};
+  static const double b = 0.21178;
+  static const Scheme bl = {2, {b, 1.0 - 2.0 * b, b}, {0.5, 0.5}};
+  static const double w1 = 1.0 / (2.0 - std::cbrt(2.0)), w0 = 1.0 - 2.0 * w1;
+  static const Scheme y4 = {3, {0.5 * w1, 0.5 * (w1 + w0), 0.5 * (w0 + w1), 0.5 * w1}, {w1, w0, w1}};
+  return kind == FZW_INT_BLANES2 ? bl : kind == FZW_INT_YOSHIDA4 ? y4 : lf;
+}
+
 // ------------------------------------------------------------------ NUTS
 namespace {
 
@@ -1040,9 +1061,10 @@ void run_nuts(fzw_plan* p, float* nu, float* u, const float* z_nu, const float* 
   pa.dtable = p->dtable_tmp;
   pa.ne = p->R * 4;
   pa.nfree = p->nfree;
-  auto vec = [&](int op) {
-    for (auto& g : segs) launch_nuts_vec(a, g, op, s);
+  auto vec = [&](int op, float frac = 1.f) {
+    for (auto& g : segs) launch_nuts_vec(a, g, op, frac, s);
   };
+  const Scheme& sc = scheme_of(p->integrator);
   auto scalar = [&](int mode, int j, int k, int nchk) { launch_nuts_scalar(a, sa, C, mode, j, k, nchk, s); };
   auto gradient = [&] {
     launch_params(pa, C, 0, 0.f, kEBlk, nullptr, s);
@@ -1063,10 +1085,12 @@ void run_nuts(fzw_plan* p, float* nu, float* u, const float* z_nu, const float* 
     vec(kNutsOpBegin);
     const int nleaf = 1 << j;
     for (int k = 0; k < nleaf; ++k) {
-      vec(kNutsOpKick);
-      vec(kNutsOpDrift);
-      gradient();
-      vec(kNutsOpKick);
+      for (int st = 0; st < sc.stages; ++st) {
+        vec(kNutsOpKick, (float)sc.kick[st]);
+        vec(kNutsOpDrift, (float)sc.drift[st]);
+        gradient();
+      }
+      vec(kNutsOpKick, (float)sc.kick[sc.stages]);
       vec(kNutsOpEnergy);
       scalar(kNutsLeaf, j, k, 0);
       const NutsLeafPlan lp = leaf_plan(k);
@@ -1264,27 +1288,6 @@ fzw_status fzw_set_sampling(fzw_plan* p, const int* tie, int n_free, const doubl
     }
     p->graphs.clear();
   });
-}
-
-// Splitting schemes of one integration step, K(a_0) D(b_1) K(a_1) ... D(b_m)
-// K(a_m), the gradient evaluated after every drift (Section 2.2 names
-// second- and fourth-order HMC and the variant of Blanes, Casas & Sanz-Serna
-// 2014): kick-drift-kick; the two-stage splitting with b = 0.21178; three
-// leapfrog steps of w1, w0, w1 with w1 = 1/(2 - 2^(1/3)), w0 = 1 - 2 w1
-// (Yoshida 1990), adjacent kicks merged.
-struct Scheme {
-  int stages;
-  double kick[4];
-  double drift[3];
-};
-
-static const Scheme& scheme_of(int kind) {
-  static const Scheme lf = {1, {0.5, 0.5}, {1.0}};
-  static const double b = 0.21178;
-  static const Scheme bl = {2, {b, 1.0 - 2.0 * b, b}, {0.5, 0.5}};
-  static const double w1 = 1.0 / (2.0 - std::cbrt(2.0)), w0 = 1.0 - 2.0 * w1;
-  static const Scheme y4 = {3, {0.5 * w1, 0.5 * (w1 + w0), 0.5 * (w0 + w1), 0.5 * w1}, {w1, w0, w1}};
-  return kind == FZW_INT_BLANES2 ? bl : kind == FZW_INT_YOSHIDA4 ? y4 : lf;
 }
 
 static void enqueue_trajectory(fzw_plan* p, float* nu, float* u, float* p_nu, float* p_u, const float* base,

@@ -12,9 +12,12 @@ probability, 1e-3 relative in a U-turn dot product), or whose perturbed
 oracle runs disagree on the tree, are not compared; the test needs at least
 three compared draws per case.  Compared: the tree depth, the leapfrog steps
 and the divergence flag exactly; the potential at the new state within 1e-5;
-the acceptance statistic within 2e-3 plus the spread of the perturbed oracle
+the acceptance statistic within 5e-3 plus the spread of the perturbed oracle
 runs (a leaf whose energy sits on a steep stretch of the potential, such as a
-tracer in a nearly empty cell, moves it by a few 1e-2); the displacement of
+tracer in a nearly empty cell, moves it by a few 1e-2; a particle within
+FP32 rounding of a cell face at some leaf changes that leaf's gradient and
+the rest of the trajectory at the 1e-4 level, which moves it by a few 1e-3);
+the displacement of
 the new state within 1e-3 normwise (bit-exact when the start point is
 kept)."""
 import dataclasses
@@ -63,12 +66,14 @@ def _oracle_potential(m, w, ch, mu, sig, counts, shape, noise=0.0, seed=0):
 # model.  Steps near the stability limit of the stiffest modes (0.1 here)
 # make the trajectory itself chaotic: a 1e-6 change of the gradient then
 # moves late leaves' energies by O(1), so they are not used.
-CASES = [("c0fd", None, 0.03, 4, 12), ("c0fd", None, 0.04, 8, 4), ("c0fd", None, 0.3, 5, 8), ("c2", 32, 0.004, 4, 6)]
+CASES = [("c0fd", None, 0.03, 4, 12, "leapfrog"), ("c0fd", None, 0.04, 8, 4, "leapfrog"),
+         ("c0fd", None, 0.3, 5, 8, "leapfrog"), ("c2", 32, 0.004, 4, 6, "leapfrog"),
+         ("c0fd", None, 0.05, 4, 8, "blanes2"), ("c0fd", None, 0.05, 4, 6, "yoshida4")]
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: "%s-%s-eps%g-d%d" % c[:4])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "%s-%s-eps%g-d%d-%s" % (c[:4] + c[5:]))
 def test_transition_matches_oracle(case):
-    name, n, eps, md, n_draws = case
+    name, n, eps, md, n_draws, scheme = case
     w, m, nu_t, nu_e, counts = mock_case(name, n)
     ch = w.chains[0]
     mu, sig = _priors(w)
@@ -84,6 +89,7 @@ def test_transition_matches_oracle(case):
     plan = plan_for(w)
     plan.set_counts(0, dev_counts(counts))
     plan.set_sampling(_tie(w), mu, sig)
+    plan.set_integrator(scheme)
     base = dev(ch.bias[None])
     t_minv = torch.ones(nv, dtype=torch.float32, device="cuda")
     t_minv_u = dev(minv_u[None])
@@ -91,9 +97,11 @@ def test_transition_matches_oracle(case):
     compared = 0
     for seed in range(n_draws):
         z, uni = _draws(ch, seed, q0.size, md)
-        ref = nuts.transition(pg, q0, z.astype(np.float64), minv, eps, uni.astype(np.float64), md, start=start)
+        ref = nuts.transition(pg, q0, z.astype(np.float64), minv, eps, uni.astype(np.float64), md, start=start,
+                              scheme=scheme)
         alts = [nuts.transition(_oracle_potential(m, w, ch, mu, sig, counts, nu0.shape, 1e-6, 100 * seed + v), q0,
-                                z.astype(np.float64), minv, eps, uni.astype(np.float64), md, start=start)
+                                z.astype(np.float64), minv, eps, uni.astype(np.float64), md, start=start,
+                                scheme=scheme)
                 for v in range(3)]
         robust = all((a.depth, a.n_leapfrog, a.diverging) == (ref.depth, ref.n_leapfrog, ref.diverging)
                      and abs(a.potential - ref.potential) < 1e-6 * abs(ref.potential) for a in alts)
@@ -115,7 +123,7 @@ def test_transition_matches_oracle(case):
         compared += 1
         assert (int(st[0]), int(st[1]), bool(st[2])) == (ref.depth, ref.n_leapfrog, ref.diverging)
         assert abs(float(host(pot)[0]) - ref.potential) < 1e-5 * abs(ref.potential)
-        assert abs(float(host(acc)[0]) - ref.accept_stat) < 2e-3 + 2 * spread
+        assert abs(float(host(acc)[0]) - ref.accept_stat) < 5e-3 + 2 * spread
         if moved:
             assert e_q < 1e-3
         else:

@@ -198,3 +198,23 @@ def test_window_schedule_of_a_thousand_warmup_iterations():
     50, 100, 200 and 500 iterations, then a 50-iteration terminal buffer."""
     assert nuts.window_ends(1000) == [100, 150, 250, 450, 950]
     assert nuts.window_ends(100) == []
+
+
+@pytest.mark.parametrize("scheme", ["blanes2", "yoshida4"])
+def test_samples_keep_a_gaussian_invariant_with_other_schemes(scheme):
+    """Leaves made with the two-stage or the fourth-order step: a 2-D
+    Gaussian's moments within a few Monte Carlo errors."""
+    cov = np.array([[1.0, 0.5], [0.5, 2.0]])
+    pg = _gaussian(cov)
+    rng = np.random.default_rng(21)
+    q = np.zeros(2)
+    draws = []
+    md = 5
+    for it in range(3000):
+        t = nuts.transition(pg, q, rng.standard_normal(2), 1.0, 0.4,
+                            rng.uniform(size=nuts.n_uniforms(md)), md, scheme=scheme)
+        q = t.q
+        draws.append(q)
+    x = np.array(draws[300:])
+    assert np.all(np.abs(x.mean(0)) < 0.15)
+    assert np.allclose(np.cov(x.T), cov, atol=0.15 * np.sqrt(np.outer(np.diag(cov), np.diag(cov))))
