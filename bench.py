@@ -59,6 +59,55 @@ def measured_traffic(kernel_class, n):
     return float(d["hbm_bytes_per_launch"])
 
 
+# every library source: the whole-gradient traffic figure describes all kernels
+ALL_SOURCES = ("paper_2506_03969_amd/csrc/fzw_fft.hip", "paper_2506_03969_amd/csrc/fzw_ops.hip",
+               "paper_2506_03969_amd/csrc/fzw_nuts.hip", "paper_2506_03969_amd/csrc/fzw_stats.hip",
+               "paper_2506_03969_amd/csrc/fzw_plan.cpp", "paper_2506_03969_amd/csrc/fzw_device.hpp",
+               "paper_2506_03969_amd/csrc/fzw_internal.hpp", "paper_2506_03969_amd/csrc/fzw_ops.hpp")
+
+
+def all_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in ALL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_gradient_traffic(n):
+    """HBM bytes of one whole forward+adjoint (every kernel's FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy) from the committed rocprofv3 summary,
+    or None when there is none or any library source changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_gradient_%d.json" % n)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_sha256") != all_sources_sha256():
+        return None
+    return float(d["hbm_bytes_per_gradient"])
+
+
+def gradients_only(k, workload, torch):
+    """Plan creation and k forward+adjoint evaluations, nothing else: the
+    command the whole-gradient byte counters are collected on."""
+    import numpy as np
+    import fzw_inputs as fi
+    from paper_2506_03969_amd import CosmoParams, Plan, WebParams
+    w = fi.workload(workload)
+    ch = w.chains[0]
+    plan = _plan(w, [ch], Plan, CosmoParams, WebParams)
+    plan.set_counts(0, torch.from_numpy(fi.timing_counts(ch).view(np.int16)).cuda())
+    nu = torch.from_numpy(fi.white_noise(ch, fi.ROLE_EVAL_NU).astype(np.float32).ravel()).cuda()
+    bias = torch.from_numpy(ch.bias.astype(np.float32)[None]).cuda()
+    out = (torch.empty(1, dtype=torch.float64, device="cuda"), torch.empty_like(nu), torch.empty_like(bias))
+    for _ in range(k):
+        plan.value_and_grad(nu, bias, out)
+    torch.cuda.synchronize()
+    print(json.dumps({"gradients_only": k, "workload": workload}), flush=True)
+
+
 def _plan(w, chains, Plan, CosmoParams, WebParams):
     c = w.cosmo
     cosmo = CosmoParams(c.omega_m, c.h, c.sigma8, c.n_s, c.d1, c.f_growth, c.r_s, c.rsd_axis, c.tau_sc,
@@ -209,6 +258,16 @@ def _nuts_leg(w, md, reps, torch, Plan, CosmoParams, WebParams, step_size=1e-7):
             "chain_grads_per_s": float(lv.sum(dim=1).mean()) * 1e3 / ms}
 
 
+def _hbm_measured(n, ms_per_step):
+    b = measured_gradient_traffic(n)
+    if b is None:
+        return None
+    return {"bytes_per_gradient": b, "GBps": b / (ms_per_step * 1e6), "peak": HBM_PEAK_GBS,
+            "frac": b / (ms_per_step * 1e6) / HBM_PEAK_GBS,
+            "source": "profiles/traffic_gradient_%d.json (rocprofv3 FETCH_SIZE + WRITE_SIZE over every kernel, "
+                      "scaled by a 1 GiB copy)" % n}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +280,8 @@ def main():
                     help="skip the ragged 32-chain and the 512^3 leapfrog trajectories")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
+    ap.add_argument("--gradients-only", type=int, default=0,
+                    help="only create the plan and run this many forward+adjoint evaluations (byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU path "
@@ -231,6 +292,9 @@ def main():
     import torch
     if args.copy_calibration:
         copy_calibration(torch)
+        return
+    if args.gradients_only > 0:
+        gradients_only(args.gradients_only, args.workload, torch)
         return
     import fzw_inputs as fi
     from paper_2506_03969_amd import CosmoParams, Plan, WebParams, fft_schedule
@@ -362,6 +426,7 @@ def main():
                    "mesh": n, "box": ch.box, "chains": 1},
         "batched": batched,
         "cic_atomic": cic_atomic,
+        "hbm_measured": _hbm_measured(n, ms_per_step),
         "model_bytes_per_grad": model_bytes,
         "model_GBps": model_bytes / (ms_per_step * 1e6),
         "hbm_frac_model": model_bytes / (ms_per_step * 1e6) / HBM_PEAK_GBS,
