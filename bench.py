@@ -24,7 +24,8 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, 8 TB/s
 # kernel of each timing class with the four-step FFT schedule (rocprofv3 names)
 KERNEL_SYMBOLS = {
     "z_r2c": "fzw::zpass4_r2c_kernel<{n}>", "z_c2r": "fzw::zpass4_c2r_kernel<{n}>",
-    "y_mix": "fzw::xy4_pass_kernel<{n}, 1, 1, *>", "x_mix": "fzw::xy4_pass_kernel<{n}, 0, 1, *>",
+    "y_mix": "fzw::xy4_pass_kernel<{n}, 1, 1, false>", "x_mix": "fzw::xy4_pass_kernel<{n}, 0, 1, false>",
+    "y_mix_multi": "fzw::xy4_pass_kernel<{n}, 1, 1, true>", "x_mix_multi": "fzw::xy4_pass_kernel<{n}, 0, 1, true>",
     "y_pure": "fzw::xy4_pure_kernel<{n}, 1, *>", "x_pure": "fzw::xy4_pure_kernel<{n}, 0, *>",
     "lpt_fwd": "fzw::lpt_fwd_z4_kernel<{n}>", "lpt_bwd": "fzw::lpt_bwd_z4_kernel<{n}>",
     "cic_adjoint": "fzw::cic_adjoint_kernel", "voxel_fwd": "fzw::voxel_fwd_kernel<{w}>",

@@ -320,8 +320,8 @@ fzw_status fzw_set_fft_schedule(int mesh_n, int z, int xy, int pure);
 enum {
   FZW_K_ZR2C = 0,        /* z-axis real-to-complex FFT pass */
   FZW_K_ZC2R = 1,        /* z-axis complex-to-real FFT pass */
-  FZW_K_YMIX = 2,        /* strided y pass with spectral multipliers / mixing */
-  FZW_K_XMIX = 3,        /* strided x pass with spectral multipliers / mixing */
+  FZW_K_YMIX = 2,        /* strided y pass with spectral multipliers / mixing, one input */
+  FZW_K_XMIX = 3,        /* strided x pass with spectral multipliers / mixing, one input */
   FZW_K_YPURE = 4,       /* pure y transforms (persistent kernel) */
   FZW_K_XPURE = 5,       /* pure x transforms (persistent kernel) */
   FZW_K_LPT_FWD = 6,     /* LPT pointwise step with its z transforms, forward */
@@ -331,7 +331,9 @@ enum {
   FZW_K_VOXEL_FWD = 10,  /* per-voxel web memberships and bias */
   FZW_K_LIKE = 11,       /* negative-binomial likelihood pass */
   FZW_K_VOXEL_BWD = 12,  /* per-voxel adjoint of web, bias and likelihood */
-  FZW_K_COUNT = 13
+  FZW_K_YMIX_MULTI = 13, /* strided y mixing pass with several inputs */
+  FZW_K_XMIX_MULTI = 14, /* strided x mixing pass with several inputs */
+  FZW_K_COUNT = 15
 };
 /* Turn per-launch timing on (1) or off (0): every later launch of the plan's
  * kernels (outside HIP graphs) is bracketed by HIP events on the plan's

@@ -369,7 +369,9 @@ struct Pass {
 thread_local fzw_plan* t_plan = nullptr;   // plan whose stages are being enqueued
 
 void run_pass(const Group& g, int axis, Pass& ps, int nmid, hipStream_t s) {
-  Timed tm(t_plan, axis == 0 ? FZW_K_XMIX : FZW_K_YMIX, (ps.a.nin + ps.a.nout) * spec_bytes(g));
+  // single- and multi-input passes run different kernels: separate classes
+  const int klass = ps.a.nin > 1 ? (axis == 0 ? FZW_K_XMIX_MULTI : FZW_K_YMIX_MULTI) : (axis == 0 ? FZW_K_XMIX : FZW_K_YMIX);
+  Timed tm(t_plan, klass, (ps.a.nin + ps.a.nout) * spec_bytes(g));
   ps.a.nmid = nmid;
   ps.a.chain_stride = g.ns;
   ps.a.tabs = g.tabs;

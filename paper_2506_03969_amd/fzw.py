@@ -21,7 +21,7 @@ _lib = None
 WEB_PHI, WEB_DELTA = 0, 1
 RSD_RADIAL = 3          # rsd_axis value: radial RSD about an observer at the box centre
 KERNEL_CLASSES = ("z_r2c", "z_c2r", "y_mix", "x_mix", "y_pure", "x_pure", "lpt_fwd", "lpt_bwd", "cic_deposit",
-                  "cic_adjoint", "voxel_fwd", "likelihood", "voxel_bwd")
+                  "cic_adjoint", "voxel_fwd", "likelihood", "voxel_bwd", "y_mix_multi", "x_mix_multi")
 # classes that are one kernel (template) each; the CIC deposit is a sequence
 SINGLE_KERNEL_CLASSES = tuple(c for c in KERNEL_CLASSES if c != "cic_deposit")
 
