@@ -407,6 +407,36 @@ def main():
             nuts_leg["ms_per_transition"], nuts_leg["leaves_per_transition"], nuts_leg["ms_per_leaf"],
             nuts_leg["chain_grads_per_s"]), file=sys.stderr, flush=True)
 
+    # validation statistics of a 256^3 field (multipoles, 32 shells; reduced
+    # bispectrum at k1 = 0.1, k2 = 0.2 h/Mpc over 9 opening angles)
+    stats_leg = None
+    if not args.no_trajectories:
+        ps = _plan(w, [ch], Plan, CosmoParams, WebParams)
+        delta = torch.from_numpy(fi.white_noise(ch, fi.ROLE_MISC).astype(np.float32).ravel()).cuda()
+        kf = 2 * np.pi / ch.box
+        thetas = list(np.linspace(0.05, np.pi - 0.05, 9))
+        ps.power_multipoles(delta, None, k_lo=kf, dk=kf, nbins=32, mesh_n=n)
+        ps.bispectrum(delta, 0.1, 0.2, 2 * kf, thetas, mesh_n=n)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(ps.stream)
+        for _ in range(5):
+            ps.power_multipoles(delta, None, k_lo=kf, dk=kf, nbins=32, mesh_n=n)
+        e1.record(ps.stream)
+        torch.cuda.synchronize()
+        ms_pk = e0.elapsed_time(e1) / 5
+        e0.record(ps.stream)
+        ps.bispectrum(delta, 0.1, 0.2, 2 * kf, thetas, mesh_n=n)
+        e1.record(ps.stream)
+        torch.cuda.synchronize()
+        stats_leg = {"mesh": n, "multipoles_ms": ms_pk, "multipole_shells": 32,
+                     "bispectrum_ms": e0.elapsed_time(e1), "bispectrum_angles": len(thetas)}
+        print("# statistics at %d^3: P0/P2 %.3f ms, bispectrum (9 angles) %.3f ms" % (
+            n, ms_pk, stats_leg["bispectrum_ms"]), file=sys.stderr, flush=True)
+        del ps
+        torch.cuda.empty_cache()
+
     cpu = None if args.no_cpu else cpu_baseline(w)
     model_bytes = fi.bytes_model(n, w.web.n_webs)
     line = {
@@ -433,6 +463,7 @@ def main():
         "hbm_frac_model": model_bytes / (ms_per_step * 1e6) / HBM_PEAK_GBS,
         "trajectories": trajectories,
         "nuts": nuts_leg,
+        "statistics": stats_leg,
         "algorithmic_GBps_all_kernels": total_alg / (ms_per_step * 1e6),
         "hbm_frac_algorithmic": total_alg / (ms_per_step * 1e6) / HBM_PEAK_GBS,
         "kernel_classes": classes,
