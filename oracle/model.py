@@ -13,7 +13,7 @@ the paper; fixed here and in the GPU library alike):
     map whose adjoint is the same chain with the conjugate multiplier;
   * rfftn is unnormalised and irfftn carries 1/N^3 (numpy convention).
 
-Readings where the paper is silent or garbled (all listed in the design doc):
+Readings where the paper is silent or garbled:
   * 2LPT: Psi = -D1 grad phi1 + D2 grad phi2, lap phi1 = delta_L,
     lap phi2 = sum_{i<j} (phi1_ii phi1_jj - phi1_ij^2), D2 = -3/7 D1^2.
   * spherical collapse: div Psi_SC = 3 (sqrt(max(1 - 2 D1 delta_L / 3, 0)) - 1),

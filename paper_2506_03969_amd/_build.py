@@ -9,7 +9,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libfzw.so")
 SOURCES = ["fzw_fft.hip", "fzw_ops.hip", "fzw_nuts.hip", "fzw_stats.hip", "fzw_plan.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
-         # packed FP32 instructions stay off (see the note in the design doc)
+         # packed FP32 instructions (v_pk_*_f32) stay off: hipcc would form them
+         # from scalar and float2 code by itself
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 

@@ -859,65 +859,137 @@ __device__ __forceinline__ float nb_cancel(float x) {
   return x / (1.f + x) - log1pf(x);
 }
 
-// The likelihood pass in float32 arithmetic per voxel with float64 sums, the
-// cancelling terms rewritten so that no digits are lost:
+// S(n, beta) = sum_{1<=m<n} ln(1 + m/beta) in float64: products of up to 8
+// factors, one logarithm each.
+__device__ __noinline__ double nb_log_rising_tail(int n, float beta) {
+  const double rb = 1.0 / (double)beta;
+  double s = 0.0;
+  for (int m0 = 1; m0 < n; m0 += 8) {
+    double q = 1.0;
+    const int m1 = min(n, m0 + 8);
+    for (int m = m0; m < m1; ++m) q = fma(q, (double)m * rb, q);
+    s += log(q);
+  }
+  return s;
+}
+
+// Orders the LDS accesses of one wavefront (no cross-wave barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The likelihood pass in float32 arithmetic for what only the gradient uses,
+// float64 sums, and float64 wherever a float32 rounding would be the same in
+// many voxels.  lnP adds ~N^3 terms up to ~1e8, so a rounding error shared by
+// many voxels is multiplied by their number, and it changes at random when
+// the state moves (~1 in lnP at 512^3: enough to bias Metropolis decisions).
+// Two such sources:
+//  * beta and n alone: all voxels of a saturated web region share beta.  With
+//      lnGamma(n+beta) - lnGamma(beta) = n ln beta + S,
+//      S = sum_{1<=m<n} ln(1 + m/beta),
+//    the per-voxel term is S + n ln nbar - (beta + n) ln(1 + nbar/beta) -
+//    lnGamma(n+1) (the last constant, dropped): n ln beta cancels, S vanishes
+//    for n <= 1 and is taken in float64, and beta + n is formed in float64.
+//  * ln nbar = ln C + log f rounded to float32: log f is itself a float32, so
+//    in one binade every voxel's ln nbar rounds by the same ln C-dependent
+//    amount r.  nbar = expf(float(ln nbar)) is used as it is, and
+//    ln(1 + nbar/beta) gets the first-order correction r nbar/(beta + nbar)
+//    in float64.
+// Every other float32 rounding depends on the voxel's own nbar and averages
+// out over voxels.
+// S is needed for ~1 voxel in 6 (n >= 2) but costs a float64 logarithm, so each
+// wavefront queues (n, beta) of those voxels in a ring of 128 LDS slots and
+// evaluates S once 64 are queued, one per lane (the loop runs in whole
+// wavefronts for this; the rest is drained at the end).
+// The gradient terms:
 //   d lnP/d beta = [psi(n+beta) - psi(beta) - n/(beta+nbar)] + f(nbar/beta)
 // (the same quantity as psi(n+beta) - psi(beta) - ln(1 + nbar/beta) +
 // (nbar - n)/(beta + nbar), with the part that cancels to -x^2/2 for small
-// x = nbar/beta evaluated by f), lnGamma(n+beta) - lnGamma(beta) as
-// logarithms of 8-term products, and n ln(nbar/beta) from the float64
-// ln nbar.  Counts above 64 take the float64 special functions.
+// x = nbar/beta evaluated by f) and g-hat in float32.  Counts above 64 take the
+// float64 special functions in the lane.
 __global__ __launch_bounds__(256) void likelihood32_kernel(LikeArgs a) {
   __shared__ double red[4];
+  __shared__ int2 ring[4][128];
   const long long c = blockIdx.y;
   const long long nv = a.nv;
   const double lnc = a.scal[c * kScalStride + kScalLnC];
   const bool grad = a.ghat != nullptr;
+  const int lane = threadIdx.x & 63;
+  int2* q = ring[threadIdx.x >> 6];
+  int head = 0, tail = 0;  // wave-uniform
   double sl = 0.0, sg = 0.0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x) {
-    const float lf = a.logf[c * nv + i];
-    const float beta = a.beta[c * nv + i];
-    const int n = a.counts[c * nv + i];
-    const float fn = (float)n;
-    const double lnb = lnc + (double)lf;
-    const float nb = expf((float)lnb);
-    const float x = nb / beta;
-    const float l1p = log1pf(x);
-    const float ib = 1.f / (beta + nb);
-    // lnGamma(n+beta) - lnGamma(beta) and psi(n+beta) - psi(beta) as sums over
-    // m < n of ln(beta+m) and 1/(beta+m): per 8 terms one logarithm of their
-    // product and one division of the product's derivative by it
-    float lg = 0.f, sr = 0.f;
-    double dbig = 0.0;
-    if (n <= 64) {
-      for (int m0 = 0; m0 < n; m0 += 8) {
-        float pq = 0.f, qq = 1.f;
-        const int m1 = min(n, m0 + 8);
-        for (int m = m0; m < m1; ++m) {
-          const float bm = beta + (float)m;
-          pq = fmaf(pq, bm, qq);
-          qq *= bm;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long wb = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63); wb < nv; wb += stride) {
+    const long long i = wb + lane;
+    bool queue = false;
+    int n = 0;
+    float beta = 1.f;
+    if (i < nv) {
+      const float lf = a.logf[c * nv + i];
+      beta = a.beta[c * nv + i];
+      n = a.counts[c * nv + i];
+      const float fn = (float)n;
+      const double lnb = lnc + (double)lf;
+      const float lnbf = (float)lnb;
+      const float nb = expf(lnbf);
+      const float x = nb / beta;
+      const float l1p = log1pf(x);
+      const float ib = 1.f / (beta + nb);
+      const double l1pd = (double)l1p + (lnb - (double)lnbf) * (double)(nb * ib);
+      double sv = 0.0;
+      if (n > 64) sv = nb_lgamma_big_d(n, (double)beta) - (double)n * log((double)beta);
+      else queue = n >= 2;
+      sl += sv - ((double)beta + (double)n) * l1pd + (double)n * lnb;
+      const float gh = beta * (fn - nb) * ib;
+      sg += (double)gh;
+      if (a.nbar) a.nbar[c * nv + i] = nb;
+      if (grad) {
+        // psi(n+beta) - psi(beta) = sum_{m<n} 1/(beta+m): per 8 terms one
+        // division of the product's derivative by the product
+        float db;
+        if (n <= 64) {
+          float sr = 0.f;
+          for (int m0 = 0; m0 < n; m0 += 8) {
+            float pq = 0.f, qq = 1.f;
+            const int m1 = min(n, m0 + 8);
+            for (int m = m0; m < m1; ++m) {
+              const float bm = beta + (float)m;
+              pq = fmaf(pq, bm, qq);
+              qq *= bm;
+            }
+            sr += pq / qq;
+          }
+          // the first two terms are of one size with no more cancellation
+          // than ~m/beta; f is the small-x-cancelling part
+          db = (sr - fn * ib) + nb_cancel(x);
+        } else {
+          db = (float)(nb_digamma_big(n, (double)beta) - (double)l1p +
+                       ((double)nb - (double)n) / ((double)beta + (double)nb));
         }
-        lg += ::logf(qq);
-        if (grad) sr += pq / qq;
+        a.ghat[c * nv + i] = gh;
+        a.nbv[c * nv + i] = nb;
+        a.dbeta[c * nv + i] = db;
       }
-    } else {
-      lg = (float)nb_lgamma_big_d(n, (double)beta);
-      if (grad)
-        dbig = nb_digamma_big(n, (double)beta) - (double)l1p + ((double)nb - (double)n) / ((double)beta + (double)nb);
     }
-    sl += (double)lg - (double)(beta + fn) * (double)l1p + (double)n * (lnb - (double)::logf(beta));
-    const float gh = beta * (fn - nb) * ib;
-    sg += (double)gh;
-    if (a.nbar) a.nbar[c * nv + i] = nb;
-    if (grad) {
-      a.ghat[c * nv + i] = gh;
-      a.nbv[c * nv + i] = nb;
-      // psi(n+beta) - psi(beta) - n/(beta+nbar) + f(nbar/beta): the first two
-      // terms are of one size with no more cancellation than ~m/beta; f is
-      // the small-x-cancelling part
-      a.dbeta[c * nv + i] = n <= 64 ? (sr - fn * ib) + nb_cancel(x) : (float)dbig;
+    const unsigned long long m = __ballot(queue);
+    if (queue) {
+      const int rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+      q[(tail + rank) & 127] = make_int2(n, __float_as_int(beta));
     }
+    tail += __popcll(m);
+    wave_lds_sync();
+    if (tail - head >= 64) {
+      const int2 e = q[(head + lane) & 127];
+      head += 64;
+      sl += nb_log_rising_tail(e.x, __int_as_float(e.y));
+      wave_lds_sync();
+    }
+  }
+  if (lane < tail - head) {
+    const int2 e = q[(head + lane) & 127];
+    sl += nb_log_rising_tail(e.x, __int_as_float(e.y));
   }
   const double s1 = block_sum(sl, red);
   const double s2 = block_sum(sg, red);

@@ -176,7 +176,8 @@ struct fzw_plan {
   int* nuts_any_host = nullptr;       // pinned
   double* stats_buf = nullptr;        // partials and scalars of the validation statistics
   int integrator = FZW_INT_LEAPFROG;  // splitting scheme of fzw_leapfrog
-  // likelihood pass in float64 per voxel instead of compensated float32
+  // likelihood pass in float64 per voxel instead of the float32 pass (float64
+  // for the terms of lnP shared by many voxels)
   // (FZW_LIKELIHOOD_FP64=1; both sum in float64)
   bool like_fp64 = false;
 };

@@ -12,6 +12,7 @@ configuration the benchmark times.
   FP64-reduced logL along the gradient (1e-3) and a random direction (2e-2).
 """
 import dataclasses
+import os
 import sys
 
 import numpy as np
@@ -203,16 +204,46 @@ def test_512_invariants():
     # in cells that are nearly empty there, log f ~ -rho_th / x makes d/dx
     # ~ 1/x^2 huge, and no finite step sees the first-order change (the 256^3
     # gradient, which matches the oracle, behaves the same way there).
-    p.set_counts(0, dev_counts(fi.timing_counts(ch)))
+    #
+    # A second plan runs the likelihood pass in float64 per voxel.  The mean
+    # the data are drawn from is that plan's, so that the data do not depend
+    # on the default pass's rounding: the Poisson sampler takes a variable
+    # number of uniforms per voxel, and one changed mean re-draws every voxel
+    # after it.
+    os.environ["FZW_LIKELIHOOD_FP64"] = "1"
+    try:
+        p64 = plan_for(w)
+    finally:
+        os.environ.pop("FZW_LIKELIHOOD_FP64", None)
     nu = dev(fi.white_noise(ch, fi.ROLE_TRUTH_NU).astype(np.float32).ravel())
     bias = dev(ch.bias[None])
-    _, nbar = p.forward(nu, bias, want_nbar=True)
+    for q in (p, p64):
+        q.set_counts(0, dev_counts(fi.timing_counts(ch)))
+    _, nbar = p64.forward(nu, bias, want_nbar=True)
     nbar_h = host(nbar).reshape((n,) * 3)
     counts = fi.gamma_poisson_counts(nbar_h, np.full_like(nbar_h, float(ch.bias[0, fi.COL_BETA])),
                                      fi.rng_for(ch, fi.ROLE_DATA))
     del nbar, nbar_h
-    p.set_counts(0, dev_counts(counts))
+    for q in (p, p64):
+        q.set_counts(0, dev_counts(counts))
     l1, g1, b1 = [t.clone() for t in p.value_and_grad(nu, bias)]
+    # the float32 likelihood pass against the float64 one on the same data:
+    # the gradients agree to float32 rounding, and so does the change of lnP
+    # between two bias tables 1e-4 apart (what a Metropolis decision sees;
+    # rounding shared by all voxels of one beta would show here as O(1))
+    l64, g64, b64 = p64.value_and_grad(nu, bias)
+    e_l = abs(float(l1[0]) - float(l64[0])) / abs(float(l64[0]))
+    e_g = float((g1.double() - g64.double()).norm() / g64.double().norm())
+    e_b = float((b1.double() - b64.double()).norm() / b64.double().norm())
+    _say("512^3 float32 vs float64 likelihood pass: logL %.2e grad %.2e bias grad %.2e" % (e_l, e_g, e_b))
+    assert e_l < 1e-6 and e_g < 1e-5 and e_b < 1e-4
+    rb = torch.from_numpy(np.random.default_rng(7).standard_normal(tuple(bias.shape)).astype(np.float32)).cuda()
+    bias2 = bias * (1 + 1e-4 * rb)
+    d32 = float(p.forward(nu, bias2)[0]) - float(l1[0])
+    d64 = float(p64.forward(nu, bias2)[0]) - float(l64[0])
+    _say("512^3 change of logL over a 1e-4 bias move: float32 pass %.6e float64 pass %.6e" % (d32, d64))
+    assert abs(d32 - d64) < 0.05
+    del p64, l64, g64, b64
     rho = p.get_field(0, 4).double()
     mass = float(rho.sum())
     del rho
@@ -224,13 +255,22 @@ def test_512_invariants():
     assert float(lf[0]) == float(l1[0])
     assert bool(torch.isfinite(g1).all()) and bool(torch.isfinite(b1).all())
 
-    # directional derivatives: central differences of the FP64-reduced logL,
-    # along the gradient (step 1e-2) and along a random direction (step 1e-3)
+    # directional derivatives: central differences of the FP64-reduced logL.
+    # Along the gradient the direction concentrates on the stiffest voxels and
+    # the O(h^2) truncation of a central difference at h = 1e-2 reaches ~1e-3
+    # relative, so the differences at h and h/2 are Richardson-extrapolated
+    # (error O(h^4)).
     gd = g1 / g1.norm()
+
+    def central(h):
+        return (float(p.forward(nu + h * gd, bias)[0]) - float(p.forward(nu - h * gd, bias)[0])) / (2 * h)
+
     h = 1e-2
-    fd = (float(p.forward(nu + h * gd, bias)[0]) - float(p.forward(nu - h * gd, bias)[0])) / (2 * h)
+    fd1, fd2 = central(h), central(h / 2)
+    fd = (4.0 * fd2 - fd1) / 3.0
     an = float(g1.double().norm())
-    _say("512^3 along the gradient: FD %.6e adjoint %.6e rel %.2e" % (fd, an, abs(fd - an) / abs(an)))
+    _say("512^3 along the gradient: FD(h) %.6e FD(h/2) %.6e extrapolated %.6e adjoint %.6e rel %.2e"
+         % (fd1, fd2, fd, an, abs(fd - an) / abs(an)))
     assert abs(fd - an) < 1e-3 * abs(an)
     # along a random direction of nu the check is only coarse: the forward
     # logL carries FP32 noise of ~2e-9 relative (~0.4 of 1.7e8), i.e. ~2e2 on a
@@ -246,9 +286,11 @@ def test_512_invariants():
     _say("512^3 random direction: FD %.6e adjoint %.6e rel %.2e" % (fd, an, abs(fd - an) / abs(an)))
     assert abs(fd - an) < 0.25 * abs(an)
     # along a random relative change of the bias table the likelihood is
-    # smooth and the difference converges: held to 1e-3
+    # smooth and the difference converges: held to 1e-3 (a step of 1e-3
+    # keeps the float32 noise of the forward logL, ~3e-3, well below the
+    # difference, ~16)
     rb = torch.from_numpy(np.random.default_rng(6).standard_normal(tuple(bias.shape)).astype(np.float32)).cuda() * bias
-    hb = 3e-4
+    hb = 1e-3
     fdb = (float(p.forward(nu, bias + hb * rb)[0]) - float(p.forward(nu, bias - hb * rb)[0])) / (2 * hb)
     anb = float(torch.sum(b1.double() * rb.double()))
     _say("512^3 random bias direction: FD %.6e adjoint %.6e rel %.2e" % (fdb, anb, abs(fdb - anb) / abs(anb)))
