@@ -859,19 +859,39 @@ __device__ __forceinline__ float nb_cancel(float x) {
   return x / (1.f + x) - log1pf(x);
 }
 
-// S(n, beta) = sum_{1<=m<n} ln(1 + m/beta) in float64: products of up to 8
-// factors, one logarithm each.
-__device__ __noinline__ double nb_log_rising_tail(int n, float beta) {
-  const double rb = 1.0 / (double)beta;
-  double s = 0.0;
-  for (int m0 = 1; m0 < n; m0 += 8) {
-    double q = 1.0;
-    const int m1 = min(n, m0 + 8);
-    for (int m = m0; m < m1; ++m) q = fma(q, (double)m * rb, q);
-    s += log(q);
+// Running product of factors 1 + m/beta in float64, kept as a mantissa in
+// [1/2, 1) and a binary exponent, so that the logarithm of all the factors a
+// lane takes is formed once at the end: sum_k ln q_k = ln(prod_k q_k).
+struct LogProduct {
+  double mant = 1.0;
+  int expo = 0;
+  // multiply by prod_{1<=m<n} (1 + m/beta), n <= 64: four factors at a time
+  // (a factor is below 2^133 for any normal float beta > 0, so four of them
+  // times a mantissa below 1 stay finite), renormalised after each four
+  __device__ __forceinline__ void rising_tail(int n, float beta) {
+    // 1/beta: the float reciprocal (relative error ~1e-7) and two Newton
+    // steps, each squaring the error, to float64 rounding
+    const double b = (double)beta;
+    double rb = (double)__builtin_amdgcn_rcpf(beta);
+    rb = rb * fma(-b, rb, 2.0);
+    rb = rb * fma(-b, rb, 2.0);
+    double q = mant;
+    for (int m0 = 1; m0 < n; m0 += 4) {
+      const double d0 = (double)m0;
+      const double f0 = fma(d0, rb, 1.0);
+      const double f1 = m0 + 1 < n ? fma(d0 + 1.0, rb, 1.0) : 1.0;
+      const double f2 = m0 + 2 < n ? fma(d0 + 2.0, rb, 1.0) : 1.0;
+      const double f3 = m0 + 3 < n ? fma(d0 + 3.0, rb, 1.0) : 1.0;
+      int e;
+      q = frexp(q * ((f0 * f1) * (f2 * f3)), &e);
+      expo += e;
+    }
+    mant = q;
   }
-  return s;
-}
+  __device__ __forceinline__ double log() const {
+    return ::log(mant) + fma((double)expo, 0.6931471805599453094, (double)expo * 2.3190468138462996e-17);
+  }
+};
 
 // Orders the LDS accesses of one wavefront (no cross-wave barrier).
 __device__ __forceinline__ void wave_lds_sync() {
@@ -899,10 +919,15 @@ __device__ __forceinline__ void wave_lds_sync() {
 //    in float64.
 // Every other float32 rounding depends on the voxel's own nbar and averages
 // out over voxels.
-// S is needed for ~1 voxel in 6 (n >= 2) but costs a float64 logarithm, so each
-// wavefront queues (n, beta) of those voxels in a ring of 128 LDS slots and
-// evaluates S once 64 are queued, one per lane (the loop runs in whole
-// wavefronts for this; the rest is drained at the end).
+// S is needed only where n >= 2 and takes a loop over n, so each wavefront
+// queues (n, beta) of those voxels in LDS rings of 128 slots and multiplies
+// their factors once 64 are queued, one voxel per lane; counts up to 9 and
+// counts from 10 to 64 have rings of their own, so that one long loop does
+// not hold up a batch of short ones (the voxel loop runs in whole wavefronts
+// for this; what is left is drained at the end).  Each lane keeps the product
+// of all factors it has taken (LogProduct) and adds its logarithm once, at
+// the end: the float64 logarithm per voxel would cost more than the rest of
+// the pass.
 // The gradient terms:
 //   d lnP/d beta = [psi(n+beta) - psi(beta) - n/(beta+nbar)] + f(nbar/beta)
 // (the same quantity as psi(n+beta) - psi(beta) - ln(1 + nbar/beta) +
@@ -911,14 +936,16 @@ __device__ __forceinline__ void wave_lds_sync() {
 // float64 special functions in the lane.
 __global__ __launch_bounds__(256) void likelihood32_kernel(LikeArgs a) {
   __shared__ double red[4];
-  __shared__ int2 ring[4][128];
+  __shared__ int2 ring[4][2][128];
   const long long c = blockIdx.y;
   const long long nv = a.nv;
   const double lnc = a.scal[c * kScalStride + kScalLnC];
   const bool grad = a.ghat != nullptr;
   const int lane = threadIdx.x & 63;
-  int2* q = ring[threadIdx.x >> 6];
-  int head = 0, tail = 0;  // wave-uniform
+  int2* qs = ring[threadIdx.x >> 6][0];   // 2 <= n <= 9
+  int2* qb = ring[threadIdx.x >> 6][1];   // 10 <= n <= 64
+  int hs = 0, ts = 0, hb = 0, tb = 0;     // heads and tails, wave-uniform
+  LogProduct prod;
   double sl = 0.0, sg = 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long wb = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63); wb < nv; wb += stride) {
@@ -973,24 +1000,38 @@ __global__ __launch_bounds__(256) void likelihood32_kernel(LikeArgs a) {
         a.dbeta[c * nv + i] = db;
       }
     }
-    const unsigned long long m = __ballot(queue);
+    const bool small = queue && n <= 9;
+    const unsigned long long ms = __ballot(small);
+    const unsigned long long mb = __ballot(queue && !small);
     if (queue) {
-      const int rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-      q[(tail + rank) & 127] = make_int2(n, __float_as_int(beta));
+      const unsigned long long mm = small ? ms : mb;
+      const int rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mm, 0u));
+      (small ? qs : qb)[((small ? ts : tb) + rank) & 127] = make_int2(n, __float_as_int(beta));
     }
-    tail += __popcll(m);
+    ts += __popcll(ms);
+    tb += __popcll(mb);
     wave_lds_sync();
-    if (tail - head >= 64) {
-      const int2 e = q[(head + lane) & 127];
-      head += 64;
-      sl += nb_log_rising_tail(e.x, __int_as_float(e.y));
-      wave_lds_sync();
+    if (ts - hs >= 64) {
+      const int2 e = qs[(hs + lane) & 127];
+      hs += 64;
+      prod.rising_tail(e.x, __int_as_float(e.y));
     }
+    if (tb - hb >= 64) {
+      const int2 e = qb[(hb + lane) & 127];
+      hb += 64;
+      prod.rising_tail(e.x, __int_as_float(e.y));
+    }
+    wave_lds_sync();
   }
-  if (lane < tail - head) {
-    const int2 e = q[(head + lane) & 127];
-    sl += nb_log_rising_tail(e.x, __int_as_float(e.y));
+  if (lane < ts - hs) {
+    const int2 e = qs[(hs + lane) & 127];
+    prod.rising_tail(e.x, __int_as_float(e.y));
   }
+  if (lane < tb - hb) {
+    const int2 e = qb[(hb + lane) & 127];
+    prod.rising_tail(e.x, __int_as_float(e.y));
+  }
+  sl += prod.log();
   const double s1 = block_sum(sl, red);
   const double s2 = block_sum(sg, red);
   if (threadIdx.x == 0) {
