@@ -154,6 +154,40 @@ def test_gradient(gcase):
     assert e_b < max(GRAD_TOL, 20 * fb)
 
 
+def test_likelihood_count_range():
+    """Counts across every branch of the likelihood pass against the oracle:
+    0 and 1, 2..9 and 10..64 (the two queues of its float64 sum, with
+    partial batches left for the end) and above 64 (the float64 special
+    functions).  One voxel in ten gets 8..59 more tracers, one in a hundred
+    65..399 more."""
+    w, m, nu, counts, p, bias = _gpu_forward("c2", 32, "truth")
+    rng = np.random.default_rng(77)
+    c = counts.astype(np.int64).reshape(-1).copy()
+    idx = rng.permutation(c.size)
+    k = c.size // 10
+    c[idx[:k]] += rng.integers(8, 60, k)
+    c[idx[k:k + k // 10]] += rng.integers(65, 400, k // 10)
+    c = c.reshape(counts.shape)
+    print("counts: n<=1 %d, 2..9 %d, 10..64 %d, >64 %d" % (
+        np.sum(c <= 1), np.sum((c >= 2) & (c <= 9)), np.sum((c >= 10) & (c <= 64)), np.sum(c > 64)))
+    assert np.sum(c > 64) > 0 and np.sum((c >= 10) & (c <= 64)) > 0
+    p.set_counts(0, dev_counts(c))
+    logl, dnu, dbias = p.value_and_grad(dev(nu.ravel()), bias)
+    lf = p.forward(dev(nu.ravel()), bias)
+    ref_l, ref_dnu, ref_db = m.value_and_grad(nu, w.chains[0].bias, c)
+    e_l = abs(float(host(logl)[0]) - ref_l) / abs(ref_l)
+    g = host(dnu).reshape(nu.shape)
+    b = host(dbias).reshape(ref_db.shape)
+    e_nu, e_bn = relnorm(g, ref_dnu), relnorm(b, ref_db)
+    fn = 0.0
+    if e_nu >= GRAD_TOL or e_bn >= GRAD_TOL:
+        fn, _ = _oracle_floor(m, nu, w.chains[0].bias, c, ref_dnu, ref_db)
+    print("count range: logL=%.2e dnu=%.2e dbias=%.2e (floor %.2e)" % (e_l, e_nu, e_bn, fn))
+    assert float(host(lf)[0]) == float(host(logl)[0])
+    assert e_l < LOGL_TOL
+    assert e_nu < max(GRAD_TOL, 10 * fn) and e_bn < max(GRAD_TOL, 10 * fn)
+
+
 def test_bitwise_determinism():
     w, m, nu, counts, p, bias = _gpu_forward("c2", 32, "eval")
     x = dev(nu.ravel())
