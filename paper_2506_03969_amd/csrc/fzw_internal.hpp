@@ -36,7 +36,7 @@ constexpr int kMaxOut = 6;
 // 2: 2^(-c q); 3: 1 - 2^(-c q); 4: 2^(-c q)/k^2; 5: l 2^(-c q), with
 // k^2 = kf^2 q (and 0 for the 1/k^2 forms at q = 0); c holds the Gaussian's
 // k^2 r^2 / 2 coefficient divided by ln 2.
-constexpr int kRadialTables = 6;
+constexpr int kRadialTables = 10;
 struct RadialForms {
   signed char kind[kRadialTables];
   float c[kRadialTables];

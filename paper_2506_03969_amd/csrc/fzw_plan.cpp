@@ -40,7 +40,12 @@ struct Error : std::runtime_error {
   } while (0)
 
 // radial tables
-enum { TAB_H = 0, TAB_INVK2 = 1, TAB_K = 2, TAB_1MK = 3, TAB_WEB0 = 4, TAB_WEB1 = 5, NTAB = 6 };
+// radial tables; the last four are products of two others, formed in FP64 so
+// that a multiplier needs one gather instead of two
+enum {
+  TAB_H = 0, TAB_INVK2 = 1, TAB_K = 2, TAB_1MK = 3, TAB_WEB0 = 4, TAB_WEB1 = 5,
+  TAB_K_INVK2 = 6, TAB_1MK_INVK2 = 7, TAB_H_INVK2 = 8, TAB_H_K = 9, NTAB = 10
+};
 static_assert(NTAB == kRadialTables, "one closed form per table");
 // stage scratch spectra
 constexpr int kNSpec = 13;
@@ -267,6 +272,10 @@ void build_tables(fzw_plan* p, Group& g) {
     tab[(size_t)TAB_INVK2 * g.tab_stride + q] = (float)ik2;
     tab[(size_t)TAB_K * g.tab_stride + q] = (float)kern;
     tab[(size_t)TAB_1MK * g.tab_stride + q] = (float)(1.0 - kern);
+    tab[(size_t)TAB_K_INVK2 * g.tab_stride + q] = (float)(kern * ik2);
+    tab[(size_t)TAB_1MK_INVK2 * g.tab_stride + q] = (float)((1.0 - kern) * ik2);
+    tab[(size_t)TAB_H_INVK2 * g.tab_stride + q] = (float)(h * ik2);
+    tab[(size_t)TAB_H_K * g.tab_stride + q] = (float)(h * kern);
     for (int w = 0; w < p->W; ++w) {
       const double r = p->web.smooth_r[w];
       const double wg = std::exp(-0.5 * k2 * r * r);
@@ -290,6 +299,8 @@ void build_tables(fzw_plan* p, Group& g) {
     g.rf.c[TAB_K] = (float)cs;
     g.rf.kind[TAB_1MK] = 3;
     g.rf.c[TAB_1MK] = (float)cs;
+    g.rf.kind[TAB_K_INVK2] = 4;
+    g.rf.c[TAB_K_INVK2] = (float)cs;
     for (int w = 0; w < p->W; ++w) {
       const double r = p->web.smooth_r[w];
       g.rf.c[TAB_WEB0 + w] = (float)(0.5 * kf * kf * r * r / std::log(2.0));
@@ -551,9 +562,9 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     pure_pass(g, Y, false, &sp[2], 2, s);
     Pass ps;
     ps.in(sp[2], true).in(sp[3], true).in(sp[1], false);
-    ps.a.A[0][0] = spec((float)(3.0 / 7.0) * d1 * d1 * invn3, 0.f, NONE, NONE, TAB_K, TAB_INVK2);
-    ps.a.A[0][1] = spec(-invn3, 0.f, NONE, NONE, TAB_1MK, TAB_INVK2);
-    ps.a.A[0][2] = spec(d1 * invn3, 0.f, NONE, NONE, TAB_K, TAB_INVK2);
+    ps.a.A[0][0] = spec((float)(3.0 / 7.0) * d1 * d1 * invn3, 0.f, NONE, NONE, TAB_K_INVK2, NONE);
+    ps.a.A[0][1] = spec(-invn3, 0.f, NONE, NONE, TAB_1MK_INVK2, NONE);
+    ps.a.A[0][2] = spec(d1 * invn3, 0.f, NONE, NONE, TAB_K_INVK2, NONE);
     ps.out(sp[4], true).out(sp[5], true);
     ps.a.B[0][0] = spec(0.f, 1.f, X, NONE, NONE, NONE);  // i k_x
     ps.a.B[1][0] = spec_const(1.f);
@@ -751,7 +762,7 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
     ps.out(sp[2], true).out(sp[3], true).out(sp[4], false);
     ps.a.B[0][0] = spec((float)(3.0 / 7.0) * d1 * d1 * invn3, 0.f, NONE, NONE, TAB_K, NONE);
     ps.a.B[1][0] = spec(-invn3, 0.f, NONE, NONE, TAB_1MK, NONE);
-    ps.a.B[2][0] = spec(d1, 0.f, NONE, NONE, TAB_H, TAB_K);   // direct d nu_k (times N^3)
+    ps.a.B[2][0] = spec(d1, 0.f, NONE, NONE, TAB_H_K, NONE);   // direct d nu_k (times N^3)
     run_pass(g, X, ps, 1, s);
     pure_pass(g, Y, true, &sp[2], 2, s);
   }
@@ -782,9 +793,9 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
     hessian_yf(g, &sp[5], sp[5], sp[6], sp[7], s);
     Pass ps;
     ps.in(sp[5], true).in(sp[6], true).in(sp[7], true).in(sp[4], false);
-    ps.a.A[0][0] = spec(invn3, 0.f, X, X, TAB_H, TAB_INVK2);
-    ps.a.A[0][1] = spec(invn3, 0.f, X, NONE, TAB_H, TAB_INVK2);
-    ps.a.A[0][2] = spec(invn3, 0.f, NONE, NONE, TAB_H, TAB_INVK2);
+    ps.a.A[0][0] = spec(invn3, 0.f, X, X, TAB_H_INVK2, NONE);
+    ps.a.A[0][1] = spec(invn3, 0.f, X, NONE, TAB_H_INVK2, NONE);
+    ps.a.A[0][2] = spec(invn3, 0.f, NONE, NONE, TAB_H_INVK2, NONE);
     ps.a.A[0][3] = spec_const(invn3);
     ps.out(sp[0], true);
     ps.a.B[0][0] = spec_const(1.f);
