@@ -116,8 +116,8 @@ fzw_status fzw_set_counts(fzw_plan* plan, int chain, const uint16_t* counts);
  *   nbar  (device, may be NULL) float32 expected counts, packed chains
  *   logl  (device) float64 [n_chains]
  * The negative-binomial pass runs in float32 per voxel with float64 sums, and
- * in float64 wherever a rounding would be shared by many voxels (so that
- * differences of logl between nearby states keep float64-like accuracy); the
+ * in float64 wherever a rounding would be shared by many voxels (such errors
+ * add up coherently and move logl by O(1) at 512^3 between nearby states); the
  * environment variable FZW_LIKELIHOOD_FP64=1, read at fzw_plan_create, runs
  * it in float64 per voxel instead.  fzw_forward and fzw_value_and_grad give
  * the same logl bit for bit. */
