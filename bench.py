@@ -285,7 +285,7 @@ def main():
                     help="only create the plan and run this many forward+adjoint evaluations (byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU path "
+        print("bench.py runs on one GPU only: it measures the single-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
