@@ -910,8 +910,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 //      lnGamma(n+beta) - lnGamma(beta) = n ln beta + S,
 //      S = sum_{1<=m<n} ln(1 + m/beta),
 //    the per-voxel term is S + n ln nbar - (beta + n) ln(1 + nbar/beta) -
-//    lnGamma(n+1) (the last constant, dropped): n ln beta cancels, S vanishes
-//    for n <= 1 and is taken in float64, and beta + n is formed in float64.
+//    lnGamma(n+1) (the last depends on the counts alone and is summed once,
+//    when they are set): n ln beta cancels, S vanishes for n <= 1 and is
+//    taken in float64, and beta + n is formed in float64.
 //  * ln nbar = ln C + log f rounded to float32: log f is itself a float32, so
 //    in one binade every voxel's ln nbar rounds by the same ln C-dependent
 //    amount r.  nbar = expf(float(ln nbar)) is used as it is, and
