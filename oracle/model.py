@@ -306,6 +306,34 @@ class Model:
         pa, pb = p_webs
         return (pa[:, None, :] * pb[None, :, :]).reshape(16, -1)
 
+    # ------------------------------------------------------- web and bias
+    def web_bias(self, delta, bias):
+        """Section 2.8 and Eq. 'local_bias' on a density contrast delta: web
+        tensors, sorted eigenvalues, sigmoid weights and memberships, region
+        probabilities, per-voxel parameters interpolated over the regions
+        (boxed equation of Section 2.8: the parameters, not the bias values,
+        are mixed) and the unnormalised bias f.  Returns the intermediates."""
+        s, g = self.s, self.g
+        bias = np.asarray(bias, dtype=np.float64)
+        tens = self.web_tensors(g.rfft(delta))
+        lams, ws, ps = [], [], []
+        for t6 in tens:
+            lam, _ = self.eigen(t6)
+            w, p = self.memberships(lam)
+            lams.append(lam), ws.append(w), ps.append(p)
+        preg = self.regions(ps)                     # [R, M]
+        theta = bias.T @ preg                       # [4, M]: alpha, eps, rho, beta
+        alpha, eps, rho_th, beta = theta
+        d = np.asarray(delta).reshape(-1)
+        x = np.maximum(1.0 + d, s.x_floor)
+        lnx = np.log(x)
+        ell_ = lnx - np.log(rho_th)
+        u = np.exp(eps * ell_)
+        logf = alpha * lnx - u                      # Eq. 'local_bias' (signed eps)
+        f = np.exp(logf)
+        return dict(tens=tens, lams=lams, ws=ws, ps=ps, preg=preg, theta=theta, x=x, lnx=lnx,
+                    ellr=ell_, u=u, logf=logf, f=f)
+
     # ----------------------------------------------------------------- forward
     def forward(self, nu, bias, counts=None):
         """Run the forward model.  Returns a dict with every intermediate; when
@@ -318,26 +346,11 @@ class Model:
         pos = self.positions(psi)
         rho = self.cic(pos)
         delta = rho - 1.0
-        delta_hat = g.rfft(delta)
-        tens = self.web_tensors(delta_hat)
-        lams, vecs, ws, ps = [], [], [], []
-        for t6 in tens:
-            lam, _ = self.eigen(t6)
-            w, p = self.memberships(lam)
-            lams.append(lam), ws.append(w), ps.append(p)
-        preg = self.regions(ps)                     # [R, M]
-        theta = bias.T @ preg                       # [4, M]: alpha, eps, rho, beta
-        alpha, eps, rho_th, beta = theta
-        d = delta.reshape(-1)
-        x = np.maximum(1.0 + d, s.x_floor)
-        lnx = np.log(x)
-        ell_ = lnx - np.log(rho_th)
-        u = np.exp(eps * ell_)
-        logf = alpha * lnx - u                      # Eq. 'local_bias' (signed eps)
-        f = np.exp(logf)
-        st.update(nu=nu, bias=bias, dl_hat=dl_hat, psi=psi, pos=pos, rho=rho, delta=delta,
-                  tens=tens, lams=lams, ws=ws, ps=ps, preg=preg, theta=theta, x=x, lnx=lnx,
-                  ellr=ell_, u=u, logf=logf, f=f, **lpt)
+        st.update(nu=nu, bias=bias, dl_hat=dl_hat, psi=psi, pos=pos, rho=rho, delta=delta, **lpt)
+        st.update(self.web_bias(delta, bias))
+        theta = st["theta"]
+        beta = theta[3]
+        f, logf = st["f"], st["logf"]
         if counts is not None:
             n = np.asarray(counts, dtype=np.float64).reshape(-1)
             ntr = n.sum()
@@ -360,7 +373,10 @@ class Model:
         return st["logl"], dnu, dbias
 
     def adjoint(self, st):
-        """Hand-written reverse pass: d logL / d nu and d logL / d bias table."""
+        """Hand-written reverse pass: d logL / d nu and d logL / d bias table.
+        Also records in `st` the cotangents of two intermediates: d logL /
+        d rho ('drho', the density) and d logL / d Psi ('dpsi', the
+        displacement, per particle)."""
         s, g = self.s, self.g
         n = st["counts"]
         alpha, eps, rho_th, beta = st["theta"]
@@ -403,6 +419,7 @@ class Model:
             for (i, j), c in zip(PAIRS, comps):
                 ddelta_hat = ddelta_hat + g.hessian_factor(i, j) * m * g.rfft(c)
         ddelta = g.irfft(ddelta_hat) + dx_direct.reshape((s.n,) * 3)
+        st["drho"] = ddelta
         # CIC adjoint, then the RSD chain rule
         dpos = self.cic_adjoint(st["pos"], ddelta)
         if s.rsd_axis == RSD_RADIAL:
@@ -416,6 +433,7 @@ class Model:
         if 0 <= s.rsd_axis < 3:
             # s_ax = q_ax + (1+f) Psi_ax / dx
             dpsi[s.rsd_axis] = dpsi[s.rsd_axis] * (1.0 + s.f_growth)
+        st["dpsi"] = dpsi
         # ALPT adjoint: conjugate multipliers
         dq_hat = 0.0
         for j in range(3):

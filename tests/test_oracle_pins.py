@@ -67,16 +67,34 @@ def test_bbks_small_scale_limit():
     assert cosmology.bbks_transfer(1e-7, 0.31, 0.68) == pytest.approx(1.0, abs=1e-5)
 
 
-def test_sigma8_normalisation_independent_quadrature():
-    """The amplitude reproduces sigma8 = 0.81 when the top-hat variance is
-    re-integrated in linear k with Simpson's rule (a different integrator and
-    variable than the oracle's)."""
+def _sphere_window(k, radius, nodes=256):
+    """Fourier transform of the unit-volume sphere of the given radius,
+    computed here by quadrature of its definition: W(k) = (3/R^3) int_0^R r^2
+    sin(kr)/(kr) dr (the angular integral of exp(i k.x) over a shell is
+    4 pi r^2 sin(kr)/(kr)), Gauss-Legendre in r."""
+    x, w = np.polynomial.legendre.leggauss(nodes)
+    r = 0.5 * radius * (x + 1.0)
+    kr = np.outer(k, r)
+    j0 = np.sinc(kr / np.pi)
+    return 3.0 / radius ** 3 * (j0 * r * r) @ (0.5 * radius * w)
+
+
+def test_sigma8_normalisation_independent_window():
+    """The amplitude reproduces sigma8 = 0.81: the variance of the linear
+    density in spheres of 8 Mpc/h, sigma^2 = (1/2 pi^2) int dk k^2 P(k) W(k)^2,
+    with the sphere's window taken from its definition by quadrature (not the
+    oracle's closed form) and Simpson's rule in ln k (not the oracle's
+    adaptive integrator).  Only the amplitude and the BBKS shape come from the
+    oracle; a wrong window or normalisation integral moves sigma8."""
     cos = fi.Cosmo()
     amp = cosmology.power_amplitude(cos)
-    k = np.linspace(1e-6, 60.0, 2_000_001)
-    integrand = k * k * cosmology.linear_power(k, cos, amp) * cosmology.tophat_window(8.0 * k) ** 2
-    s2 = integrate.simpson(integrand, x=k) / (2 * np.pi ** 2)
-    assert np.sqrt(s2) == pytest.approx(0.81, rel=2e-4)
+    lnk = np.linspace(np.log(1e-5), np.log(20.0), 20001)
+    k = np.exp(lnk)
+    pk = amp * k ** cos.n_s * cosmology.bbks_transfer(k, cos.omega_m, cos.h) ** 2
+    win = _sphere_window(k, 8.0)
+    assert _sphere_window(np.array([1e-6]), 8.0)[0] == pytest.approx(1.0, abs=1e-9)
+    s2 = integrate.simpson(k ** 3 * pk * win ** 2, x=lnk) / (2 * np.pi ** 2)
+    assert np.sqrt(s2) == pytest.approx(0.81, rel=1e-4)
 
 
 def test_white_noise_filter_recovers_input_power():
@@ -144,6 +162,43 @@ def test_2lpt_crossed_waves():
     assert np.allclose(psi[0], want, atol=1e-11)
     want_y = -(b / k) * np.sin(k * y) - (3.0 / 14.0) * (a * b / k) * np.sin(k * y) * np.cos(k * x)
     assert np.allclose(psi[1], want_y, atol=1e-11)
+
+
+def test_alpt_blend_at_finite_radius_mode_by_mode():
+    """Section 2.3 boxed equation: at a finite smoothing radius the ALPT
+    displacement is, mode by mode, K(k) times the pure 2LPT displacement plus
+    (1 - K(k)) times the pure spherical-collapse one, with the Gaussian
+    K = exp(-k^2 r_s^2 / 2) (r_s read as the Gaussian sigma).  The two pure
+    displacements come from the same model at r_s = 0 and r_s -> infinity
+    (pinned above by the Zel'dovich, crossed-wave and spherical-collapse
+    tests); K is computed here from the wave numbers.  A kernel of another
+    width, exp(-k^2 r_s^2), is shown to fail by a wide margin."""
+    n, box, rs = 32, 128.0, 4.0
+    m = _model(n, box, r_s=rs)
+    m0 = _model(n, box, r_s=0.0)
+    minf = _model(n, box, r_s=1e9)
+    nu = np.random.default_rng(21).standard_normal((n, n, n))
+    dl_hat = m.linear_density_hat(nu)
+    assert np.std(m.g.irfft(dl_hat)) > 1.0          # large enough that SC and 2LPT differ
+    psi = m.alpt(dl_hat)[0]
+    psi0 = m0.alpt(dl_hat)[0]
+    psiinf = minf.alpt(dl_hat)[0]
+    kf = 2 * np.pi / box
+    f = np.fft.fftfreq(n, 1.0 / n) * kf
+    fz = np.fft.rfftfreq(n, 1.0 / n) * kf
+    k2 = f[:, None, None] ** 2 + f[None, :, None] ** 2 + fz[None, None, :] ** 2
+    for width, ok in ((0.5, True), (1.0, False)):
+        kern = np.exp(-width * k2 * rs * rs)
+        worst = 0.0
+        for j in range(3):
+            got = np.fft.rfftn(psi[j])
+            want = kern * np.fft.rfftn(psi0[j]) + (1.0 - kern) * np.fft.rfftn(psiinf[j])
+            worst = max(worst, np.abs(got - want).max() / np.abs(want).max())
+        if ok:
+            assert worst < 1e-12
+        else:
+            assert worst > 1e-2
+    assert np.abs(psi0 - psiinf).max() > 0.1 * np.abs(psi0).max()
 
 
 def test_spherical_collapse_one_dimensional_wave():
@@ -388,6 +443,97 @@ def test_memberships_partition_of_unity_and_hard_limit():
     assert ok.sum() > 4000
     onehot = np.eye(4)[w_class]
     assert np.allclose(ph.T[ok], onehot[ok], atol=1e-12)
+
+
+def _separable_case(n=16, box=100.0, amps=(0.3, -0.25, 0.2), mode=2):
+    """delta = sum_j a_j cos(k x_j): every Fourier mode lies on one axis, so
+    the web tensors of either kind (no smoothing) are diagonal, with entries
+    a_j cos(k x_j) (Phi-web: k_j k_j / k^2 = 1) and ell^2 k^2 a_j cos(k x_j)
+    (delta-web)."""
+    x, y, z = _coords(n, box)
+    k = 2 * np.pi / box * mode
+    diag = [a * np.cos(k * v) for a, v in zip(amps, (x, y, z))]
+    return k, sum(diag), diag
+
+
+def _closed_form_f(webs_diag, table, steep, th, x):
+    """f at every voxel from the paper's equations, given the diagonal
+    entries of each web's tensor: eigenvalues sorted descending (Appendix B
+    order), sigmoid weights w_n = 1/(1 + exp(-s (lambda_n - th)))
+    (Eq. 'sigmoid'), memberships V, S, F, K = 1-w1, w1-w2, w2-w3, w3
+    (Eq. 'soft_cweb_p'), regions p_jk = p_j p_k over two webs, parameters
+    interpolated as sum_r p_r theta_r (boxed equation of Section 2.8), then
+    f = x^alpha exp(-(x/rho)^eps) (Eq. 'local_bias').  Returns f, the
+    region probabilities and the per-region f values."""
+    ps = []
+    for diag in webs_diag:
+        lam = -np.sort(-np.stack([d.ravel() for d in diag], axis=1), axis=1)
+        w = 1.0 / (1.0 + np.exp(-steep * (lam - th)))
+        ps.append(np.stack([1.0 - w[:, 0], w[:, 0] - w[:, 1], w[:, 1] - w[:, 2], w[:, 2]]))
+    preg = ps[0] if len(ps) == 1 else np.einsum("jm,km->jkm", ps[0], ps[1]).reshape(16, -1)
+    alpha, eps, rho = [(preg * table[:, c][:, None]).sum(0) for c in (0, 1, 2)]
+    f = x ** alpha * np.exp(-(x / rho) ** eps)
+    f_r = np.stack([x ** a * np.exp(-(x / r) ** e) for a, e, r in table[:, :3]])
+    return f, preg, f_r
+
+
+def test_parameter_interpolation_soft_memberships():
+    """Boxed equation of Section 2.8: the bias parameters (alpha, eps, rho,
+    beta) are interpolated per voxel with the region memberships and f is
+    evaluated once with them.  On an axis-separable field the eigenvalues are
+    known in closed form, so f follows from the paper's equations alone; with
+    an unequal table and steepness 20 many voxels sit between classes, and
+    mixing the per-region values f_r instead of the parameters misses by far
+    more than the tolerance (checked)."""
+    n, box = 16, 100.0
+    m = _model(n, box)
+    k, delta, diag = _separable_case(n, box)
+    table = np.array([[0.9, -0.5, 0.10, 2.0], [1.1, -1.0, 0.20, 4.0],
+                      [1.4, -2.0, 0.40, 6.0], [1.8, -3.0, 0.60, 8.0]])
+    got = m.web_bias(delta, table)
+    x = 1.0 + delta.ravel()
+    f, preg, f_r = _closed_form_f([diag], table, m.s.steepness, m.s.lambda_th, x)
+    assert np.allclose(got["preg"], preg, rtol=0, atol=1e-12)
+    assert np.allclose(got["f"], f, rtol=1e-11, atol=0)
+    mixed = (preg * f_r).sum(0)
+    assert np.abs(mixed / f - 1).max() > 1e-2
+    soft = (preg.max(0) < 0.9).mean()
+    assert soft > 0.2                                  # a fifth of the voxels are fuzzy
+
+
+def test_parameter_interpolation_sixteen_regions():
+    """The two-web model (Phi-web x delta-web, region 4 j + k): with an
+    unequal 16-row table, f at steepness 20 follows the closed form of the
+    products of the two webs' memberships, and at steepness 10^6 every voxel
+    (eigenvalues off the threshold) takes the f of its hard region, whose web
+    classes count the eigenvalues above the threshold (Eq. 'hard_cweb')."""
+    n, box, ell = 16, 100.0, 11.25     # ell^2 k^2 = 2: the delta-web classes differ from the Phi-web ones
+    # entries a_j cos(k x_j) take the values a_j {+-1, +-0.707, 0}: amplitudes
+    # that put Phi-web entries on both sides of the threshold
+    k, delta, diag = _separable_case(n, box, amps=(0.12, -0.13, 0.09))
+    kw = dict(kinds=(fi.WEB_PHI, fi.WEB_DELTA), smooth_r=(0.0, 0.0), ell=(0.0, ell))
+    rng = np.random.default_rng(31)
+    table = np.stack([rng.uniform(0.8, 1.8, 16), -rng.uniform(0.5, 3.0, 16), rng.uniform(0.1, 0.6, 16),
+                      rng.uniform(2.0, 9.0, 16)], axis=1)
+    ddiag = [ell * ell * k * k * d for d in diag]
+    x = 1.0 + delta.ravel()
+    soft = _model(n, box, **kw)
+    f, preg, f_r = _closed_form_f([diag, ddiag], table, soft.s.steepness, soft.s.lambda_th, x)
+    assert np.allclose(soft.web_bias(delta, table)["f"], f, rtol=1e-11, atol=0)
+    assert np.abs((preg * f_r).sum(0) / f - 1).max() > 1e-2
+    hard = _model(n, box, steepness=1e6, **kw)
+    th = hard.s.lambda_th
+    cls = []
+    margin = np.full(n ** 3, np.inf)
+    for dg in (diag, ddiag):
+        vals = np.stack([d.ravel() for d in dg], axis=1)
+        cls.append((vals > th).sum(1))
+        margin = np.minimum(margin, np.abs(vals - th).min(1))
+    region = 4 * cls[0] + cls[1]
+    ok = margin > 1e-4
+    assert ok.mean() > 0.9 and len(np.unique(region[ok])) >= 6
+    want = f_r[region, np.arange(n ** 3)]
+    assert np.allclose(hard.web_bias(delta, table)["f"][ok], want[ok], rtol=1e-12, atol=0)
 
 
 def test_sixteen_regions_partition_of_unity():
