@@ -109,12 +109,12 @@ def gradients_only(k, workload, torch):
     print(json.dumps({"gradients_only": k, "workload": workload}), flush=True)
 
 
-def _plan(w, chains, Plan, CosmoParams, WebParams):
+def _plan(w, chains, Plan, CosmoParams, WebParams, checkpoint=False):
     c = w.cosmo
     cosmo = CosmoParams(c.omega_m, c.h, c.sigma8, c.n_s, c.d1, c.f_growth, c.r_s, c.rsd_axis, c.tau_sc,
                         c.x_floor)
     web = WebParams(w.web.kinds, w.web.smooth_r, w.web.ell, w.web.steepness, w.web.lambda_th)
-    return Plan([ch.n for ch in chains], [ch.box for ch in chains], cosmo, web)
+    return Plan([ch.n for ch in chains], [ch.box for ch in chains], cosmo, web, checkpoint=checkpoint)
 
 
 def _time_steps(plan, nu, bias, out, steps, torch):
@@ -131,28 +131,37 @@ def _time_steps(plan, nu, bias, out, steps, torch):
     return ev0.elapsed_time(ev1) / 1e3, wall
 
 
-def cpu_baseline(w):
-    """The FP64 oracle (as it stands) on a bounded sample: one forward + adjoint
-    of the same model at 128^3 with the same cell size, scaled by the 8x voxel
-    count to the 256^3 step."""
-    import numpy as np
+def cpu_baseline(w, n_cpu=128, reps=3):
+    """The FP64 oracle (as it stands) on a bounded sample of the same model:
+    forward + adjoint at n_cpu^3 with the same cell size, one untimed warm-up
+    then the median of `reps` runs, reported as the rate at that mesh (not
+    scaled to another size).  Threads: the host's share (OMP_NUM_THREADS when
+    set) for the FFTs; the batched 3x3 eigen-solver and the element-wise
+    NumPy work run on one thread."""
+    import statistics
     import fzw_inputs as fi
     from oracle import model as om
-    ncpu = os.cpu_count() or 1
+    ncpu = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
     om.set_workers(ncpu)
-    ws = fi.small_variant(w, 128)
+    ws = fi.small_variant(w, n_cpu)
     ch = ws.chains[0]
     m = om.Model(om.Settings.from_workload(ws.cosmo, ws.web, ch))
     nu = fi.white_noise(ch, fi.ROLE_EVAL_NU)
     counts = fi.timing_counts(ch)
-    t0 = time.perf_counter()
-    st = m.forward(nu, ch.bias, counts)
-    m.adjoint(st)
-    dt = time.perf_counter() - t0
-    scale = (w.chains[0].n / 128) ** 3
-    return {"value": 1.0 / (dt * scale), "unit": "grads/s", "cores": ncpu, "kind": "oracle",
-            "sample": "one FP64 forward+adjoint at 128^3 (same model and cell size) took %.1f s; "
-                      "scaled by %dx voxels to the 256^3 step" % (dt, scale)}
+    times = []
+    for _ in range(reps + 1):
+        t0 = time.perf_counter()
+        st = m.forward(nu, ch.bias, counts)
+        m.adjoint(st)
+        times.append(time.perf_counter() - t0)
+        del st
+    med = statistics.median(times[1:])
+    return {"value": 1.0 / med, "unit": "grads/s at %d^3" % n_cpu, "cores": ncpu, "kind": "oracle",
+            "mesh": n_cpu, "seconds_per_gradient": med, "voxel_grads_per_s": n_cpu ** 3 / med,
+            "sample": "FP64 forward+adjoint of the same model (%d webs, %d regions, RSD, same cell size) at "
+                      "%d^3, L=%g: median of %d runs after one warm-up (%s s)" % (
+                          ws.web.n_webs, ws.n_regions, n_cpu, ch.box, reps,
+                          ", ".join("%.2f" % t for t in times[1:]))}
 
 
 def copy_calibration(torch, gib=1, reps=5):
@@ -168,7 +177,7 @@ def copy_calibration(torch, gib=1, reps=5):
           flush=True)
 
 
-def _trajectory(w, steps, reps, torch, Plan, CosmoParams, WebParams, step_size=1e-5):
+def _trajectory(w, steps, reps, torch, Plan, CosmoParams, WebParams, step_size=1e-5, checkpoint=False):
     """Time graph-captured leapfrog trajectories of every chain of workload w
     (ragged meshes allowed): returns ms per leapfrog step (one gradient of
     every chain) over `reps` trajectories after one warm-up trajectory.  The
@@ -176,7 +185,7 @@ def _trajectory(w, steps, reps, torch, Plan, CosmoParams, WebParams, step_size=1
     gradient is large: a small step keeps every timed state close to it."""
     import numpy as np
     import fzw_inputs as fi
-    plan = _plan(w, w.chains, Plan, CosmoParams, WebParams)
+    plan = _plan(w, w.chains, Plan, CosmoParams, WebParams, checkpoint)
     for c, ch in enumerate(w.chains):
         plan.set_counts(c, torch.from_numpy(fi.timing_counts(ch).view(np.int16)).cuda())
     mu, sig = fi.prior_arrays(w)
@@ -201,9 +210,10 @@ def _trajectory(w, steps, reps, torch, Plan, CosmoParams, WebParams, step_size=1
     ev1.record(plan.stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / (reps * steps)
+    ws = plan.workspace_bytes
     del plan
     torch.cuda.empty_cache()
-    return ms
+    return ms, ws
 
 
 def _nuts_leg(w, md, reps, torch, Plan, CosmoParams, WebParams, step_size=1e-7):
@@ -283,6 +293,8 @@ def main():
                     help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
     ap.add_argument("--gradients-only", type=int, default=0,
                     help="only create the plan and run this many forward+adjoint evaluations (byte counters)")
+    ap.add_argument("--trajectory-only", default="",
+                    help="only run this workload's graph-captured trajectories (c3 or c4; for kernel traces)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: it measures the single-GPU path "
@@ -296,6 +308,13 @@ def main():
         return
     if args.gradients_only > 0:
         gradients_only(args.gradients_only, args.workload, torch)
+        return
+    if args.trajectory_only:
+        import fzw_inputs as fi
+        from paper_2506_03969_amd import CosmoParams, Plan, WebParams
+        wt = fi.workload(args.trajectory_only)
+        ms, ws = _trajectory(wt, wt.leapfrog_steps, 2, torch, Plan, CosmoParams, WebParams)
+        print(json.dumps({"trajectory_only": args.trajectory_only, "ms_per_leapfrog_step": ms}), flush=True)
         return
     import fzw_inputs as fi
     from paper_2506_03969_amd import CosmoParams, Plan, WebParams, fft_schedule
@@ -382,18 +401,42 @@ def main():
     trajectories = None
     if not args.no_trajectories:
         trajectories = {}
-        for name in ("c3", "c4"):
+        for name, ck in (("c3", False), ("c4", False), ("c4", True)):
             wt = fi.workload(name)
-            ms = _trajectory(wt, wt.leapfrog_steps, 2, torch, Plan, CosmoParams, WebParams)
+            ms, ws = _trajectory(wt, wt.leapfrog_steps, 2, torch, Plan, CosmoParams, WebParams, checkpoint=ck)
             vox = sum(ch.n ** 3 for ch in wt.chains)
             model = sum(fi.bytes_model(ch.n, wt.web.n_webs, leapfrog=True) for ch in wt.chains)
-            trajectories[name] = {
+            trajectories[name + ("_checkpointed" if ck else "")] = {
                 "chains": len(wt.chains), "meshes": sorted({ch.n for ch in wt.chains}),
-                "leapfrog_steps": wt.leapfrog_steps, "ms_per_leapfrog_step": ms,
+                "leapfrog_steps": wt.leapfrog_steps, "ms_per_leapfrog_step": ms, "workspace_bytes": ws,
                 "grads_per_s": len(wt.chains) * 1e3 / ms, "voxel_grads_per_s": vox * 1e3 / ms,
                 "model_GBps": model / (ms * 1e6), "hbm_frac_model": model / (ms * 1e6) / HBM_PEAK_GBS}
-            print("# %s trajectory: %d chains, %.3f ms per leapfrog step (%.1f grads/s, %.0f GB/s model)" % (
-                name, len(wt.chains), ms, len(wt.chains) * 1e3 / ms, model / (ms * 1e6)), file=sys.stderr, flush=True)
+            print("# %s%s trajectory: %d chains, %.3f ms per leapfrog step (%.1f grads/s, %.0f GB/s model), "
+                  "workspace %.1f GB" % (name, " checkpointed" if ck else "", len(wt.chains), ms,
+                                         len(wt.chains) * 1e3 / ms, model / (ms * 1e6), ws / 1e9),
+                  file=sys.stderr, flush=True)
+
+    # batched vs single where batching matters: each c3 mesh size alone (one
+    # chain, the same 10-step graph trajectory), and the 32 chains run one
+    # after another at those rates, against the batched trajectory above
+    c3_single = None
+    if not args.no_trajectories and trajectories and "c3" in trajectories:
+        import dataclasses
+        wt = fi.workload("c3")
+        per = {}
+        for n_ in sorted({ch.n for ch in wt.chains}):
+            ch1 = next(ch for ch in wt.chains if ch.n == n_)
+            ms1, _ = _trajectory(dataclasses.replace(wt, chains=[ch1]), wt.leapfrog_steps, 2, torch, Plan,
+                                 CosmoParams, WebParams)
+            per[n_] = ms1
+        seq_ms = sum(per[ch.n] for ch in wt.chains)
+        c3_single = {"ms_per_leapfrog_step_alone": {str(k): v for k, v in per.items()},
+                     "sequential_ms_per_step_all_chains": seq_ms,
+                     "batched_ms_per_step_all_chains": trajectories["c3"]["ms_per_leapfrog_step"],
+                     "batched_over_sequential_rate": seq_ms / trajectories["c3"]["ms_per_leapfrog_step"]}
+        print("# c3 alone per leapfrog step: %s ms; the 32 chains in sequence %.2f ms vs batched %.2f ms (x%.2f)" % (
+            ", ".join("%d^3 %.3f" % kv for kv in per.items()), seq_ms, trajectories["c3"]["ms_per_leapfrog_step"],
+            c3_single["batched_over_sequential_rate"]), file=sys.stderr, flush=True)
 
     # no-U-turn transitions of the 32 ragged chains (full trees of 31 leaves)
     nuts_leg = None
@@ -462,6 +505,7 @@ def main():
         "model_GBps": model_bytes / (ms_per_step * 1e6),
         "hbm_frac_model": model_bytes / (ms_per_step * 1e6) / HBM_PEAK_GBS,
         "trajectories": trajectories,
+        "c3_batched_vs_single": c3_single,
         "nuts": nuts_leg,
         "statistics": stats_leg,
         "algorithmic_GBps_all_kernels": total_alg / (ms_per_step * 1e6),

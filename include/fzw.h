@@ -40,8 +40,12 @@
  *   - A negative status means nothing was enqueued; fzw_last_error() returns a
  *     message (thread-local, valid until the next call on the same thread).
  *     FZW_E_HIP leaves the plan unusable: destroy it.
- *   - Non-finite results are not errors: logL = -inf or NaN is written and the
- *     caller's Metropolis step rejects.
+ *   - Non-finite results are not errors: logL or H = NaN or +-inf is written,
+ *     the chain's non-finite flags are set (fzw_nonfinite_flags) and the
+ *     caller's Metropolis step rejects.  A state whose displacement field is
+ *     not finite (or moves a particle by 2^30 cells or more) is invalid: its
+ *     particles are deposited without displacement, so that no index or
+ *     weight is undefined, and its logL is NaN.
  */
 #ifndef FZW_H_
 #define FZW_H_
@@ -59,8 +63,17 @@ typedef enum {
   FZW_E_SIZE = -2,   /* unsupported mesh size */
   FZW_E_HIP = -3,    /* a HIP runtime call failed */
   FZW_E_OOM = -4,    /* workspace allocation failed; the plan is not created */
-  FZW_E_STATE = -5   /* call out of order (e.g. counts not set) */
+  FZW_E_STATE = -5,  /* call out of order (e.g. counts not set) */
+  FZW_W_NONFINITE = 1 /* fzw_check_finite: some chain's last result was not finite */
 } fzw_status;
+
+/* Bits of the per-chain non-finite flags. */
+enum {
+  FZW_NF_STATE = 1,       /* a displacement was not finite or too large: logL set to NaN */
+  FZW_NF_LOGL = 2,        /* the log-likelihood was not finite */
+  FZW_NF_GRAD = 4,        /* an entry of the bias-table gradient was not finite */
+  FZW_NF_HAMILTONIAN = 8  /* H at the start or end of a trajectory was not finite */
+};
 
 enum { FZW_WEB_PHI = 0, FZW_WEB_DELTA = 1 };
 
@@ -103,6 +116,22 @@ typedef struct fzw_plan fzw_plan;
  * the workspace (fzw_workspace_bytes) and computes the spectral tables. */
 fzw_status fzw_plan_create(fzw_plan** out, int n_chains, const int* mesh_n, const double* box_l,
                            const fzw_cosmo* cosmo, const fzw_web* web, void* stream);
+
+/* fzw_plan_create with options (flags = 0 is fzw_plan_create).
+ * FZW_PLAN_CHECKPOINT: displacement-field checkpointing for large meshes.
+ *   The workspace holds no first-order Hessian phi_ij (6 fields per chain,
+ *   and no real-space S2 and d_SC where the LPT step is fused with its z
+ *   transforms, i.e. every mesh but 96): the forward model keeps the
+ *   displacement Psi, the density and the per-voxel fields, and a gradient
+ *   evaluation recomputes phi_ij from nu before the adjoint of the LPT step,
+ *   with the forward model's own kernels on the same input, so every result
+ *   equals that of a plan without checkpointing bit for bit.  Cost: one more
+ *   r2c of nu and the passes that form phi_ij per gradient.  fzw_get_field
+ *   field 0 (delta_L, the trace of phi) is then never available.
+ * Unknown flags give FZW_E_ARG. */
+enum { FZW_PLAN_CHECKPOINT = 1 };
+fzw_status fzw_plan_create_ex(fzw_plan** out, int n_chains, const int* mesh_n, const double* box_l,
+                              const fzw_cosmo* cosmo, const fzw_web* web, void* stream, unsigned flags);
 void fzw_plan_destroy(fzw_plan* plan);
 
 /* Copy the observed counts n* of one chain (device, uint16, N^3, C order)
@@ -272,11 +301,36 @@ fzw_status fzw_bispectrum(fzw_plan* plan, int mesh_n, const float* delta, double
 enum { FZW_INT_LEAPFROG = 0, FZW_INT_BLANES2 = 1, FZW_INT_YOSHIDA4 = 2 };
 fzw_status fzw_set_integrator(fzw_plan* plan, int kind);
 
-/* Copy an intermediate field of the last forward evaluation (device
- * destination, float32 N^3 of one chain).  Fields: 0 delta_L, 1 Psi_x,
- * 2 Psi_y, 3 Psi_z, 4 rho (CIC density, mean 1), 5 log f (log of the
- * unnormalised bias), 6..11 tensor of web 0 (xx,yy,zz,xy,xz,yz), 12..17 web 1.
- * Valid until the next evaluation on the plan. */
+/* Per-chain non-finite flags (FZW_NF_* bits) of the last evaluation call:
+ * fzw_forward, fzw_value_and_grad, fzw_leapfrog (every gradient of the
+ * trajectory and both Hamiltonians) or fzw_nuts (every leaf, rejected ones
+ * included).  Each of these calls clears the flags first.
+ * fzw_nonfinite_flags enqueues a copy into `flags` (device, int32
+ * [n_chains]) on the plan's stream and returns at once.
+ * fzw_check_finite synchronises the plan's stream, copies the flags into
+ * `flags_host` (host int32 [n_chains], may be NULL) and returns
+ * FZW_W_NONFINITE if any chain has a flag set, else FZW_OK. */
+fzw_status fzw_nonfinite_flags(fzw_plan* plan, int* flags);
+fzw_status fzw_check_finite(fzw_plan* plan, int* flags_host);
+
+/* Copy an intermediate field of the last evaluation (device destination,
+ * float32 N^3 of one chain).
+ * After fzw_forward: 0 delta_L, 1 Psi_x, 2 Psi_y, 3 Psi_z (displacement,
+ * Mpc/h), 4 rho (CIC density, mean 1), 5 log f (log of the unnormalised
+ * bias), 6..11 tensor of web 0 (xx,yy,zz,xy,xz,yz), 12..17 web 1.
+ * A gradient evaluation (fzw_value_and_grad, fzw_leapfrog, fzw_nuts) reuses
+ * the displacement and tensor buffers for their cotangents: afterwards
+ * fields 4 and 5 (and 0 on meshes with the fused LPT kernels, all but 96)
+ * are still those of its last forward model, 1-3 and 6-17 are not, and the
+ * adjoint's cotangents are available instead:
+ *   FZW_FIELD_DRHO   d logL / d rho (the density cotangent, both web terms
+ *                    and the direct bias term)
+ *   FZW_FIELD_DPSI+j d logL / d Psi_j per particle (j = 0, 1, 2; the
+ *                    particle of lattice node i at index i)
+ * A field that the last call did not leave gives FZW_E_STATE (so does any
+ * field before the first evaluation, and field 0 after fzw_bispectrum,
+ * which uses its buffers).  FZW_E_ARG for a field the plan does not have. */
+enum { FZW_FIELD_DRHO = 18, FZW_FIELD_DPSI = 19 };
 fzw_status fzw_get_field(fzw_plan* plan, int chain, int field, float* out);
 
 /* Standalone batched 3-D FFTs on the plan's stream (for testing and reuse).

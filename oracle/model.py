@@ -45,7 +45,8 @@ from . import cosmology
 PAIRS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
 RSD_RADIAL = 3          # rsd_axis value selecting radial RSD about the box centre
 WEB_PHI, WEB_DELTA = 0, 1
-_WORKERS = os.cpu_count() or 1
+# FFT threads: the host's thread share where one is set, else every core
+_WORKERS = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
 
 
 def set_workers(n: int) -> None:
@@ -397,6 +398,9 @@ class Model:
         dx_direct = np.where(1.0 + d > s.x_floor, dx_direct, 0.0)
         preg = st["preg"]
         dbias = preg @ dtheta.T                     # [R, 4]
+        # the sums of the magnitudes of each entry's per-voxel terms: the
+        # scale of the rounding error of any evaluation that rounds the terms
+        st["dbias_abs"] = np.abs(preg) @ np.abs(dtheta).T
         dp = st["bias"] @ dtheta                    # [R, M]
         ps = st["ps"]
         if len(ps) == 1:

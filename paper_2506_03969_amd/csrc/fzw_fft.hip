@@ -196,6 +196,17 @@ __global__ __launch_bounds__(kThreadsXY) void xy_pass_kernel(PassArgs a, const f
         }
       }
     }
+    // the radial table shared by inputs 0..i, applied once to their sum
+    if (i == a.post_after) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int nr = freq_index(r0 + j * RS, N);
+        const int n0 = AXIS == 0 ? nr : 0, n1 = AXIS == 0 ? nb : nr;
+        const float r = radial_value(a.rf, a.post_tab, n0 * n0 + n1 * n1 + nz * nz, a.tabs, a.tab_stride);
+#pragma unroll
+        for (int m = 0; m < NMID; ++m) mid[m][j] = cscale(mid[m][j], r);
+      }
+    }
   }
 
   for (int o = 0; o < a.nout; ++o) {
@@ -394,12 +405,21 @@ __global__ __launch_bounds__(z4_lines<N>() * F4<N / 2>::N1) void lpt_fwd_z4_kern
   for (int i = t; i < M; i += NT) twh[i] = tw_half[i];
   for (int i = t; i < N; i += NT) twf[i] = tw_full[i];
   __syncthreads();
+  // a.field[0] null: phi is not stored (checkpointed plans recompute it in
+  // the adjoint); a.sout[0] null: phi only, no S2 and d_SC (that recompute).
+  // Both are kernel arguments, so the branches are uniform and the phi values
+  // come from the same instructions either way.
+  const bool store = a.field[0] != nullptr;
+  const bool lpt = a.sout[0] != nullptr;
   float2 S[N2], D[N2], v[N2];
   for (int c = 0; c < 6; ++c) {
     z4_c2r_line<N>(a.sin[c] + soff, v, ll, j, twh, twf);
-    float2* dst = reinterpret_cast<float2*>(a.field[c]) + roff;
+    if (store) {
+      float2* dst = reinterpret_cast<float2*>(a.field[c]) + roff;
 #pragma unroll
-    for (int q = 0; q < N2; ++q) dst[j + N1 * q] = v[q];
+      for (int q = 0; q < N2; ++q) dst[j + N1 * q] = v[q];
+    }
+    if (!lpt) continue;
     if (c == 0) {
 #pragma unroll
       for (int q = 0; q < N2; ++q) D[q] = v[q];
@@ -420,6 +440,7 @@ __global__ __launch_bounds__(z4_lines<N>() * F4<N / 2>::N1) void lpt_fwd_z4_kern
       for (int q = 0; q < N2; ++q) S[q] = make_float2(S[q].x - v[q].x * v[q].x, S[q].y - v[q].y * v[q].y);
     }
   }
+  if (!lpt) return;
   z4_r2c_line<N>(S, ll, j, twh, twf, a.sout[0] + soff);
   const float k = (2.f / 3.f) * a.d1;
 #pragma unroll
@@ -586,6 +607,19 @@ __global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1, 3) void xy4_pass_kernel(
         kv.n[2] = nz;
         kv.n2 = kv.n[0] * kv.n[0] + kv.n[1] * kv.n[1] + nz * nz;
         mid[m][e] = cadd(mid[m][e], cmul(spec_eval<!PF>(op, kv, a.kf, nyq, a.tabs, a.tab_stride, a.rf), val[e]));
+      }
+    }
+    // the radial table shared by inputs 0..i, applied once to their sum
+    if (i == a.post_after) {
+#pragma unroll
+      for (int e = 0; e < N2; ++e) {
+        const int nr = freq_index(rowB(e), N);
+        const int n0 = AXIS == 0 ? nr : 0, n1 = AXIS == 0 ? nb : nr;
+        const int q = n0 * n0 + n1 * n1 + nz * nz;
+        const float r = PF ? a.tabs[a.post_tab * a.tab_stride + min(q, a.tab_stride - 1)]
+                           : radial_value(a.rf, a.post_tab, q, a.tabs, a.tab_stride);
+#pragma unroll
+        for (int m = 0; m < NMID; ++m) mid[m][e] = cscale(mid[m][e], r);
       }
     }
   }

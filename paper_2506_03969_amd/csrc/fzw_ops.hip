@@ -95,10 +95,17 @@ struct RadialFrame {
 // (plus the radial shift when enabled), lower corner (cx, cy, cz) wrapped into
 // the box and fractional offsets (tx, ty, tz).  FRAME also returns the radial
 // frame and d before the shift, for the adjoint.
+// A displacement (after the redshift-space shift) that is not finite or
+// reaches 2^30 cells has no cell: it is replaced by zero, so that every index
+// stays inside the mesh and every weight is finite, and cic_locate returns
+// false; the deposit kernels then flag the chain's state as invalid (its
+// log-likelihood becomes NaN).
+constexpr float kMaxCells = 1073741824.f;
 template <bool FRAME = false>
-__device__ __forceinline__ void cic_locate(const CicArgs& a, int p, int n, int& cx, int& cy, int& cz,
+__device__ __forceinline__ bool cic_locate(const CicArgs& a, int p, int n, int& cx, int& cy, int& cz,
                                            float& tx, float& ty, float& tz, RadialFrame* fr = nullptr,
                                            float* d0 = nullptr) {
+  bool ok = true;
   const int q = (int)fast_div((unsigned)p, a.dn);
   const int iz = p - q * n;
   const int ix = (int)fast_div((unsigned)q, a.dn);
@@ -129,6 +136,11 @@ __device__ __forceinline__ void cic_locate(const CicArgs& a, int p, int n, int& 
       dz = dz + s * rz;
       if (FRAME) *fr = RadialFrame{rx, ry, rz, r2, s};
     }
+    // (comparisons with NaN are false)
+    if (!(fabsf(dx) < kMaxCells && fabsf(dy) < kMaxCells && fabsf(dz) < kMaxCells)) {
+      dx = dy = dz = 0.f;
+      ok = false;
+    }
     const float fx = floorf(dx), fy = floorf(dy), fz = floorf(dz);
     tx = dx - fx;
     ty = dy - fy;
@@ -140,6 +152,7 @@ __device__ __forceinline__ void cic_locate(const CicArgs& a, int p, int n, int& 
   cx = wrap_index(cx, n);
   cy = wrap_index(cy, n);
   cz = wrap_index(cz, n);
+  return ok;
 }
 
 // Adds one to ctr[key] for every lane of the wave that passes `valid`, with
@@ -188,12 +201,14 @@ __global__ __launch_bounds__(256) void cic_count_kernel(CicArgs a) {
     const long long p = p0 + (threadIdx.x & 63);
     const bool valid = p < nv;
     int key = 0;
+    bool bad = false;
     if (valid) {
       int cx, cy, cz;
       float tx, ty, tz;
-      cic_locate(b, (int)p, n, cx, cy, cz, tx, ty, tz);
+      bad = !cic_locate(b, (int)p, n, cx, cy, cz, tx, ty, tz);
       key = cx * n + cy;
     }
+    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(a.flags + c, FZW_NF_STATE);
     wave_count<false>(count, key, valid);
   }
 }
@@ -442,7 +457,7 @@ __global__ void cic_atomic_kernel(CicArgs a) {
     float tx, ty, tz;
     RadialFrame fr;
     float d0[3];
-    cic_locate<true>(b, (int)p, n, cx, cy, cz, tx, ty, tz, &fr, d0);
+    if (!cic_locate<true>(b, (int)p, n, cx, cy, cz, tx, ty, tz, &fr, d0)) atomicOr(a.flags + c, FZW_NF_STATE);
     const int nx = cx + 1 == n ? 0 : cx + 1;
     const int ny = cy + 1 == n ? 0 : cy + 1;
     const int nz = cz + 1 == n ? 0 : cz + 1;
@@ -693,7 +708,11 @@ __device__ __forceinline__ void web_memberships(const float lam[3], float s, flo
 // sum_{m<n} ln(beta+m) = lnGamma(n+beta) - lnGamma(beta), and its beta
 // derivative sum_{m<n} 1/(beta+m).
 __device__ __forceinline__ double digamma_d(double x) {
-  // recurrence up to x >= 8, then the asymptotic series (Abramowitz & Stegun 6.3.18)
+  // recurrence up to x >= 8, then the asymptotic series (Abramowitz & Stegun 6.3.18);
+  // only x > 0 occurs (x = n + beta with beta > 0): anything else, NaN
+  // included, returns NaN before the recurrence, which would not end for
+  // x = -inf
+  if (!(x > 0.0)) return __builtin_nan("");
   double r = 0.0;
   while (x < 8.0) {
     r -= 1.0 / x;
@@ -1173,7 +1192,9 @@ __global__ void finalize_kernel(FinalArgs a) {
     s1 = block_sum(s1, red);
     s2 = block_sum(s2, red);
     if (threadIdx.x == 0) {
-      const double logl = s1 - sc[kScalLgConst];
+      double logl = s1 - sc[kScalLgConst];
+      if (a.flags[c] & FZW_NF_STATE) logl = __builtin_nan("");
+      if (!isfinite(logl)) a.flags[c] |= FZW_NF_LOGL;
       sc[kScalLogL] = logl;
       sc[kScalG] = s2;
       if (a.logl) a.logl[c] = logl;
@@ -1191,7 +1212,10 @@ __global__ void finalize_table_kernel(FinalArgs a) {
   double s = 0.0;
   for (int i = threadIdx.x; i < a.nblk; i += blockDim.x) s += a.partial[(c * a.nblk + i) * ne + e];
   s = block_sum(s, red);
-  if (threadIdx.x == 0) a.dtable[c * ne + e] = (float)s;
+  if (threadIdx.x == 0) {
+    a.dtable[c * ne + e] = (float)s;
+    if (!isfinite(s)) atomicOr(a.flags + c, FZW_NF_GRAD);
+  }
 }
 
 void launch_voxel_fwd(int w, const VoxelArgs& a, int chains, int nblk, hipStream_t s) {
@@ -1322,6 +1346,7 @@ __global__ void params_kernel(ParamArgs a, int mode, float frac, int nblk_energy
         h += 0.5 * (double)mi[f] * (double)pu[f] * (double)pu[f];
       }
       hout[c] = h;
+      if (!isfinite(h)) a.flags[c] |= FZW_NF_HAMILTONIAN;
     }
   }
 }

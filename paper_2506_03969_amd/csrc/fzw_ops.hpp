@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/fzw.h"
+
 namespace fzw {
 
 // per-chain float64 scalars kept on the device
@@ -51,6 +53,7 @@ struct CicArgs {
   float4* sorted;        // [chains][nv] (tx, ty, tz, bits of (by << 16 | bz)) in column order
   unsigned long long* acc;  // [chains][nv] fixed-point accumulator (atomic deposit), kept zero
   float* rho;            // [chains][nv]
+  int* flags;            // [chains] non-finite flags (FZW_NF_*), set by the deposit
   const float* drho;     // adjoint input
   float* dpsi[3];        // adjoint output
 };
@@ -96,6 +99,7 @@ struct FinalArgs {
   double* logl;
   float* dtable;
   int ne;
+  int* flags;            // [chains] non-finite flags (FZW_NF_*)
 };
 
 struct LeapArgs {
@@ -124,6 +128,7 @@ struct ParamArgs {
   const double* scal;
   const double* epartial;
   int ne, nfree;
+  int* flags;               // [chains] non-finite flags (FZW_NF_*)
 };
 
 // ---------------------------------------------------------------- NUTS

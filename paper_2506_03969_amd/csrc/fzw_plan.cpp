@@ -125,6 +125,9 @@ using namespace fzw;
 
 struct fzw_plan {
   int n_chains = 0;
+  // FZW_PLAN_CHECKPOINT: phi_ij is not kept between the forward model and the
+  // adjoint, which recomputes it from nu (no phi buffers in the workspace)
+  bool checkpoint = false;
   int W = 1, R = 4;
   fzw_cosmo cosmo{};
   fzw_web web{};
@@ -141,6 +144,10 @@ struct fzw_plan {
   long long total_vox = 0;
   uint16_t* counts = nullptr;
   double* scal = nullptr;             // [n_chains][kScalStride]
+  int* flags = nullptr;               // [n_chains] non-finite flags (FZW_NF_*) of the last evaluation call
+  // fields fzw_get_field may return (bit = field id): what the last
+  // evaluation left in the buffers
+  unsigned long long field_valid = 0;
   double* partial = nullptr;
   size_t partial_elems = 0;
   float* dnu_tmp = nullptr;           // leapfrog gradient
@@ -334,9 +341,14 @@ void build_tables(fzw_plan* p, Group& g) {
 void alloc_group(fzw_plan* p, Group& g) {
   const size_t nf = (size_t)g.nc * g.nv;
   const size_t nsp = (size_t)g.nc * g.ns;
-  for (auto& f : g.phi) f = dalloc<float>(p, nf);
-  g.s2 = dalloc<float>(p, nf);
-  g.dsc = dalloc<float>(p, nf);
+  if (!p->checkpoint)
+    for (auto& f : g.phi) f = dalloc<float>(p, nf);
+  // S2 and d_SC exist in real space only where the LPT step is not fused
+  // with its z transforms
+  if (!p->checkpoint || !has_four_step_z(g.n)) {
+    g.s2 = dalloc<float>(p, nf);
+    g.dsc = dalloc<float>(p, nf);
+  }
   for (auto& f : g.psi) f = dalloc<float>(p, nf);
   g.rho = dalloc<float>(p, nf);
   for (int k = 0; k < 6 * p->W; ++k) g.tens[k] = dalloc<float>(p, nf);
@@ -365,6 +377,15 @@ struct Pass {
       for (auto& o : r) o = spec_zero();
     for (auto& r : a.B)
       for (auto& o : r) o = spec_zero();
+    a.post_after = -1;
+    a.post_tab = 0;
+  }
+  // inputs 0..after (given without a radial factor) share radial table tab:
+  // the pass multiplies their sum by it once
+  Pass& post(int after, int tab) {
+    a.post_after = after;
+    a.post_tab = tab;
+    return *this;
   }
   Pass& in(const float2* p, bool fft) {
     a.in_fft |= fft ? (1u << a.nin) : 0u;
@@ -486,18 +507,22 @@ void hessian_yf(const Group& g, float2* const* in6, float2* g2, float2* g1, floa
 // six phi_ij spectra `in` -> phi (stored) -> S2, d_SC spectra `out`[0..1].
 // Adjoint: dS2, dd_SC spectra `in`[0..1] and phi -> six d phi_ij spectra
 // `out`.  Returns false where the mesh has no fused kernel.
-bool lpt_z(fzw_plan* p, const Group& g, bool fwd, float2* const* in, float2* const* out, hipStream_t s) {
+// `field` are the phi_ij buffers (null in the forward model of a checkpointed
+// plan: phi is not stored); `out` null in the forward: phi only (the adjoint's
+// recompute of a checkpointed plan).
+bool lpt_z(fzw_plan* p, const Group& g, bool fwd, float2* const* in, float2* const* out, float* const* field,
+           hipStream_t s) {
   LptZArgs a{};
-  const int nin = fwd ? 6 : 2, nout = fwd ? 2 : 6;
+  const int nin = fwd ? 6 : 2, nout = fwd ? (out ? 2 : 0) : 6;
   for (int c = 0; c < nin; ++c) a.sin[c] = in[c];
-  for (int c = 0; c < 6; ++c) a.field[c] = g.phi[c];
+  for (int c = 0; c < 6; ++c) a.field[c] = field ? field[c] : nullptr;
   for (int c = 0; c < nout; ++c) a.sout[c] = out[c];
   a.spec_chain_stride = g.ns;
   a.field_chain_stride = g.nv;
   a.d1 = (float)p->cosmo.d1;
   a.tau = (float)p->cosmo.tau_sc;
   if (!has_four_step_z(g.n)) return false;
-  Timed tm(p, fwd ? FZW_K_LPT_FWD : FZW_K_LPT_BWD, (nin + nout) * spec_bytes(g) + 6 * field_bytes(g));
+  Timed tm(p, fwd ? FZW_K_LPT_FWD : FZW_K_LPT_BWD, (nin + nout) * spec_bytes(g) + (field ? 6 : 0) * field_bytes(g));
   return launch_lpt_z(g.n, fwd, a, g.nc, g.tw_half, g.tw_full, s);
 }
 
@@ -514,37 +539,51 @@ void zi(const Group& g, float2* const* in, float* const* out, int k, hipStream_t
 constexpr int X = 0, Y = 1, Z = 2, NONE = -1;
 
 // ------------------------------------------------------------- forward model
+// Appendix A and Section 2.3: the delta_L spectrum h(k) rfftn(nu) (into
+// sp[1], kept in k space) and the spectra of the six first-order Hessian
+// components phi_ij = k_i k_j / k^2 delta_L (into sp[5..10]), through one x
+// pass.  The forward model starts with it; a checkpointed plan's adjoint runs
+// it again to recompute phi, with the same kernels on the same input.
+void lpt_hessian_spectra(const Group& g, const float* nu, hipStream_t s) {
+  const float invn3 = (float)(1.0 / ((double)g.nv));
+  float2* const* sp = g.spec;
+  {
+    float* src[1] = {const_cast<float*>(nu)};
+    zf(g, src, &sp[0], 1, s);
+    pure_pass(g, Y, false, &sp[0], 1, s);
+  }
+  Pass ps;
+  ps.in(sp[0], true).out(sp[1], false).out(sp[2], true).out(sp[3], true).out(sp[4], true);
+  ps.a.A[0][0] = spec(1.f, 0.f, NONE, NONE, TAB_H, NONE);
+  ps.a.B[0][0] = spec_const(1.f);
+  ps.a.B[1][0] = spec(invn3, 0.f, X, X, TAB_INVK2, NONE);
+  ps.a.B[2][0] = spec(invn3, 0.f, X, NONE, TAB_INVK2, NONE);
+  ps.a.B[3][0] = spec(invn3, 0.f, NONE, NONE, TAB_INVK2, NONE);
+  run_pass(g, X, ps, 1, s);
+  hessian_yi(g, sp[2], sp[3], sp[4], &sp[5], s);
+}
+
+// The phi_ij buffers of a plan: its own, or for a checkpointed plan the first
+// six web-tensor buffers, which are free while phi is needed (before the
+// tensors are formed in the forward model, after their cotangents have been
+// transformed in the adjoint).
+float* const* phi_buffers(const fzw_plan* p, const Group& g) { return p->checkpoint ? g.tens : g.phi; }
+
 void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, float* nbar, double* logl,
                    bool grad) {
   hipStream_t s = p->stream;
   const float invn3 = (float)(1.0 / ((double)g.nv));
   const float d1 = (float)p->cosmo.d1;
   float2** sp = g.spec;
-  // Appendix A: delta_L spectrum = h(k) rfftn(nu)
-  {
-    float* src[1] = {const_cast<float*>(nu)};
-    zf(g, src, &sp[0], 1, s);
-    pure_pass(g, Y, false, &sp[0], 1, s);
-  }
-  // Section 2.3: Hessian of the first-order potential, phi_ij = k_i k_j / k^2
-  // delta_L, in the same x pass that forms delta_L (which stays in k space)
-  {
-    Pass ps;
-    ps.in(sp[0], true).out(sp[1], false).out(sp[2], true).out(sp[3], true).out(sp[4], true);
-    ps.a.A[0][0] = spec(1.f, 0.f, NONE, NONE, TAB_H, NONE);
-    ps.a.B[0][0] = spec_const(1.f);
-    ps.a.B[1][0] = spec(invn3, 0.f, X, X, TAB_INVK2, NONE);
-    ps.a.B[2][0] = spec(invn3, 0.f, X, NONE, TAB_INVK2, NONE);
-    ps.a.B[3][0] = spec(invn3, 0.f, NONE, NONE, TAB_INVK2, NONE);
-    run_pass(g, X, ps, 1, s);
-    hessian_yi(g, sp[2], sp[3], sp[4], &sp[5], s);
-  }
-  // phi_ij to real space, 2LPT source and spherical-collapse divergence, and
-  // their spectra (one fused launch where the mesh has the four-step z pass)
-  if (!lpt_z(p, g, true, &sp[5], &sp[2], s)) {
-    zi(g, &sp[5], g.phi, 6, s);
+  lpt_hessian_spectra(g, nu, s);
+  // phi_ij to real space (stored for the adjoint unless checkpointed), 2LPT
+  // source and spherical-collapse divergence, and their spectra (one fused
+  // launch where the mesh has the four-step z pass)
+  if (!lpt_z(p, g, true, &sp[5], &sp[2], p->checkpoint ? nullptr : g.phi, s)) {
+    float* const* phi = phi_buffers(p, g);
+    zi(g, &sp[5], phi, 6, s);
     LptArgs la{};
-    for (int c = 0; c < 6; ++c) la.phi[c] = g.phi[c];
+    for (int c = 0; c < 6; ++c) la.phi[c] = phi[c];
     la.s2 = g.s2;
     la.dsc = g.dsc;
     la.d1 = d1;
@@ -560,11 +599,12 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
   // ALPT blend -> Psi (Section 2.3)
   {
     pure_pass(g, Y, false, &sp[2], 2, s);
+    // the S2 and delta_L inputs share K/k^2: applied once to their sum
     Pass ps;
-    ps.in(sp[2], true).in(sp[3], true).in(sp[1], false);
-    ps.a.A[0][0] = spec((float)(3.0 / 7.0) * d1 * d1 * invn3, 0.f, NONE, NONE, TAB_K_INVK2, NONE);
-    ps.a.A[0][1] = spec(-invn3, 0.f, NONE, NONE, TAB_1MK_INVK2, NONE);
-    ps.a.A[0][2] = spec(d1 * invn3, 0.f, NONE, NONE, TAB_K_INVK2, NONE);
+    ps.in(sp[2], true).in(sp[1], false).in(sp[3], true).post(1, TAB_K_INVK2);
+    ps.a.A[0][0] = spec_const((float)(3.0 / 7.0) * d1 * d1 * invn3);
+    ps.a.A[0][1] = spec_const(d1 * invn3);
+    ps.a.A[0][2] = spec(-invn3, 0.f, NONE, NONE, TAB_1MK_INVK2, NONE);
     ps.out(sp[4], true).out(sp[5], true);
     ps.a.B[0][0] = spec(0.f, 1.f, X, NONE, NONE, NONE);  // i k_x
     ps.a.B[1][0] = spec_const(1.f);
@@ -597,6 +637,7 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     ca.sorted = g.sorted;
     ca.rho = g.rho;
     ca.acc = g.acc;
+    ca.flags = p->flags + g.c0;
     Timed tm(p, FZW_K_CIC_DEP, 4 * field_bytes(g));
     if (p->cic_method == FZW_CIC_ATOMIC) launch_cic_deposit_atomic(ca, g.nc, s);
     else launch_cic_deposit(ca, g.nc, s);
@@ -643,6 +684,7 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     fa.partial = g.partial;
     fa.nblk = g.nblk;
     fa.scal = p->scal + (size_t)g.c0 * kScalStride;
+    fa.flags = p->flags + g.c0;
     launch_finalize(fa, g.nc, s);
     LikeArgs la{};
     la.logf = g.logf;
@@ -668,7 +710,7 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
 }
 
 // ------------------------------------------------------------------ adjoint
-void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* dbias) {
+void adjoint_group(fzw_plan* p, Group& g, const float* nu, const float* bias, float* dnu, float* dbias) {
   hipStream_t s = p->stream;
   const float invn3 = (float)(1.0 / ((double)g.nv));
   const float d1 = (float)p->cosmo.d1;
@@ -705,6 +747,7 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
     fa.scal = p->scal + (size_t)g.c0 * kScalStride;
     fa.dtable = dbias + (size_t)g.c0 * p->R * 4;
     fa.ne = p->R * 4;
+    fa.flags = p->flags + g.c0;
     launch_finalize(fa, g.nc, s);
   }
   // web adjoint: d rho_k = sum_w m_w sum_ij k_i k_j rfft(dT_ij) + rfft(d rho_direct)
@@ -714,12 +757,15 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
     zf(g, dd, &sp[12], 1, s);
     for (int w = 0; w < W; ++w) hessian_yf(g, &sp[6 * w], sp[6 * w + 0], sp[6 * w + 1], sp[6 * w + 2], s);
     pure_pass(g, Y, false, &sp[12], 1, s);
+    // web 0's three inputs share its radial multiplier: applied once to their sum
     Pass ps;
+    ps.post(2, TAB_WEB0);
     for (int w = 0; w < W; ++w) {
+      const int tb = w == 0 ? NONE : TAB_WEB0 + w;
       ps.in(sp[6 * w + 0], true).in(sp[6 * w + 1], true).in(sp[6 * w + 2], true);
-      ps.a.A[0][3 * w + 0] = spec(invn3, 0.f, X, X, TAB_WEB0 + w, NONE);
-      ps.a.A[0][3 * w + 1] = spec(invn3, 0.f, X, NONE, TAB_WEB0 + w, NONE);
-      ps.a.A[0][3 * w + 2] = spec(invn3, 0.f, NONE, NONE, TAB_WEB0 + w, NONE);
+      ps.a.A[0][3 * w + 0] = spec(invn3, 0.f, X, X, tb, NONE);
+      ps.a.A[0][3 * w + 1] = spec(invn3, 0.f, X, NONE, tb, NONE);
+      ps.a.A[0][3 * w + 2] = spec(invn3, 0.f, NONE, NONE, tb, NONE);
     }
     ps.in(sp[12], true);
     ps.a.A[0][3 * W] = spec_const(invn3);
@@ -728,6 +774,13 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
     run_pass(g, X, ps, 1, s);
     pure_pass(g, Y, true, &sp[0], 1, s);
     zi(g, &sp[0], &g.drho, 1, s);
+  }
+  // checkpointed plan: phi_ij again from nu, into the tensor buffers (free
+  // now), with the forward model's own kernels, so it equals the forward's
+  // phi bit for bit
+  if (p->checkpoint) {
+    lpt_hessian_spectra(g, nu, s);
+    if (!lpt_z(p, g, true, &sp[5], nullptr, g.tens, s)) zi(g, &sp[5], g.tens, 6, s);
   }
   // CIC adjoint -> d Psi (in place over Psi)
   {
@@ -756,9 +809,9 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
       run_pass(g, Y, pyz, 1, s);
     }
     Pass ps;
-    ps.in(sp[0], true).in(sp[1], true);
-    ps.a.A[0][0] = spec(0.f, -1.f, X, NONE, TAB_INVK2, NONE);
-    ps.a.A[0][1] = spec(1.f, 0.f, NONE, NONE, TAB_INVK2, NONE);
+    ps.in(sp[0], true).in(sp[1], true).post(1, TAB_INVK2);   // both share 1/k^2
+    ps.a.A[0][0] = spec(0.f, -1.f, X, NONE, NONE, NONE);
+    ps.a.A[0][1] = spec_const(1.f);
     ps.out(sp[2], true).out(sp[3], true).out(sp[4], false);
     ps.a.B[0][0] = spec((float)(3.0 / 7.0) * d1 * d1 * invn3, 0.f, NONE, NONE, TAB_K, NONE);
     ps.a.B[1][0] = spec(-invn3, 0.f, NONE, NONE, TAB_1MK, NONE);
@@ -769,13 +822,14 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
   // LPT pointwise adjoint and the spectra of the phi cotangents (one fused
   // launch where the mesh has the four-step z pass; otherwise d phi is formed
   // in place over phi)
-  if (!lpt_z(p, g, false, &sp[2], &sp[5], s)) {
+  float* const* phi = phi_buffers(p, g);
+  if (!lpt_z(p, g, false, &sp[2], &sp[5], phi, s)) {
     float* dst[2] = {g.s2, g.dsc};
     zi(g, &sp[2], dst, 2, s);
     LptArgs la{};
     for (int c = 0; c < 6; ++c) {
-      la.phi[c] = g.phi[c];
-      la.dphi[c] = g.phi[c];
+      la.phi[c] = phi[c];
+      la.dphi[c] = phi[c];
     }
     la.s2 = g.s2;
     la.dsc = g.dsc;
@@ -786,16 +840,16 @@ void adjoint_group(fzw_plan* p, Group& g, const float* bias, float* dnu, float* 
       Timed tm(p, FZW_K_LPT_BWD, 14 * field_bytes(g));
       launch_lpt_bwd(la, s);
     }
-    zf(g, g.phi, &sp[5], 6, s);
+    zf(g, phi, &sp[5], 6, s);
   }
   // d nu_k = h / k^2 sum_ij k_i k_j rfft(d phi_ij) + direct ALPT term
   {
     hessian_yf(g, &sp[5], sp[5], sp[6], sp[7], s);
     Pass ps;
-    ps.in(sp[5], true).in(sp[6], true).in(sp[7], true).in(sp[4], false);
-    ps.a.A[0][0] = spec(invn3, 0.f, X, X, TAB_H_INVK2, NONE);
-    ps.a.A[0][1] = spec(invn3, 0.f, X, NONE, TAB_H_INVK2, NONE);
-    ps.a.A[0][2] = spec(invn3, 0.f, NONE, NONE, TAB_H_INVK2, NONE);
+    ps.in(sp[5], true).in(sp[6], true).in(sp[7], true).in(sp[4], false).post(2, TAB_H_INVK2);   // share h/k^2
+    ps.a.A[0][0] = spec(invn3, 0.f, X, X, NONE, NONE);
+    ps.a.A[0][1] = spec(invn3, 0.f, X, NONE, NONE, NONE);
+    ps.a.A[0][2] = spec_const(invn3);
     ps.a.A[0][3] = spec_const(invn3);
     ps.out(sp[0], true);
     ps.a.B[0][0] = spec_const(1.f);
@@ -904,17 +958,37 @@ void for_groups(fzw_plan* p, F&& f) {
   for (auto& g : p->groups) HIPCHK(hipStreamWaitEvent(s0, g.gdone, 0));
 }
 
+// Fields fzw_get_field may return after a forward model or a gradient.
+// (delta_L is the trace of the stored phi_ij: a checkpointed plan keeps none)
+unsigned long long forward_fields(const fzw_plan* p) {
+  return ((1ull << (6 + 6 * p->W)) - 1ull) & (p->checkpoint ? ~1ull : ~0ull);
+}
+unsigned long long gradient_fields(const fzw_plan* p) {
+  unsigned long long m = (1ull << 4) | (1ull << 5) | (1ull << FZW_FIELD_DRHO);
+  for (int j = 0; j < 3; ++j) m |= 1ull << (FZW_FIELD_DPSI + j);
+  // delta_L is the trace of the stored phi_ij, which the adjoint overwrites
+  // where the LPT step is not fused with its z transforms
+  bool fused = true;
+  for (const auto& g : p->groups) fused = fused && has_four_step_z(g.n);
+  if (fused && !p->checkpoint) m |= 1ull;
+  return m;
+}
+
+void clear_flags(fzw_plan* p) { launch_fill_i32(p->flags, p->n_chains, 0, p->stream); }
+
 void forward_all(fzw_plan* p, const float* nu, const float* bias, float* nbar, double* logl) {
   t_plan = p;
   for_groups(p, [&](Group& g) { forward_group(p, g, nu + p->chain_off[g.c0], bias, nbar, logl, false); });
+  p->field_valid = forward_fields(p);
 }
 
 void value_and_grad_all(fzw_plan* p, const float* nu, const float* bias, double* logl, float* dnu, float* dbias) {
   t_plan = p;
   for_groups(p, [&](Group& g) {
     forward_group(p, g, nu + p->chain_off[g.c0], bias, nullptr, logl, true);
-    adjoint_group(p, g, bias, dnu + p->chain_off[g.c0], dbias);
+    adjoint_group(p, g, nu + p->chain_off[g.c0], bias, dnu + p->chain_off[g.c0], dbias);
   });
+  p->field_valid = gradient_fields(p);
 }
 
 template <class F>
@@ -1075,6 +1149,7 @@ void run_nuts(fzw_plan* p, float* nu, float* u, const float* z_nu, const float* 
   pa.dtable = p->dtable_tmp;
   pa.ne = p->R * 4;
   pa.nfree = p->nfree;
+  pa.flags = p->flags;
   auto vec = [&](int op, float frac = 1.f) {
     for (auto& g : segs) launch_nuts_vec(a, g, op, frac, s);
   };
@@ -1086,6 +1161,7 @@ void run_nuts(fzw_plan* p, float* nu, float* u, const float* z_nu, const float* 
     launch_nuts_ugrad(a, pa, tvox, C, s);
   };
   // start: gradient at the current state, momentum from the draws, H0
+  clear_flags(p);
   HIPCHK(hipMemcpyAsync(a.wq, nu, sizeof(float) * tvox, hipMemcpyDeviceToDevice, s));
   if (p->nfree > 0)
     HIPCHK(hipMemcpyAsync(a.wq + tvox, u, sizeof(float) * C * p->nfree, hipMemcpyDeviceToDevice, s));
@@ -1133,12 +1209,18 @@ const char* fzw_last_error(void) { return g_last_error.c_str(); }
 
 fzw_status fzw_plan_create(fzw_plan** out, int n_chains, const int* mesh_n, const double* box_l,
                            const fzw_cosmo* cosmo, const fzw_web* web, void* stream) {
-  if (!out || !mesh_n || !box_l || !cosmo || !web || n_chains <= 0) {
-    g_last_error = "fzw_plan_create: null argument or n_chains <= 0";
+  return fzw_plan_create_ex(out, n_chains, mesh_n, box_l, cosmo, web, stream, 0u);
+}
+
+fzw_status fzw_plan_create_ex(fzw_plan** out, int n_chains, const int* mesh_n, const double* box_l,
+                              const fzw_cosmo* cosmo, const fzw_web* web, void* stream, unsigned flags) {
+  if (!out || !mesh_n || !box_l || !cosmo || !web || n_chains <= 0 || (flags & ~(unsigned)FZW_PLAN_CHECKPOINT)) {
+    g_last_error = "fzw_plan_create: null argument, n_chains <= 0 or unknown flag";
     return FZW_E_ARG;
   }
   *out = nullptr;
   auto* p = new fzw_plan();
+  p->checkpoint = (flags & FZW_PLAN_CHECKPOINT) != 0;
   {
     const char* e = std::getenv("FZW_LIKELIHOOD_FP64");
     p->like_fp64 = e && e[0] == '1';
@@ -1202,6 +1284,8 @@ fzw_status fzw_plan_create(fzw_plan** out, int n_chains, const int* mesh_n, cons
     p->counts = dalloc<uint16_t>(p, (size_t)off);
     p->scal = dalloc<double>(p, (size_t)n_chains * kScalStride);
     HIPCHK(hipMemset(p->scal, 0, (size_t)n_chains * kScalStride * sizeof(double)));
+    p->flags = dalloc<int>(p, (size_t)n_chains);
+    HIPCHK(hipMemset(p->flags, 0, (size_t)n_chains * sizeof(int)));
     p->dnu_tmp = dalloc<float>(p, (size_t)off);
     p->table_tmp = dalloc<float>(p, (size_t)n_chains * p->R * 4);
     p->dtable_tmp = dalloc<float>(p, (size_t)n_chains * p->R * 4);
@@ -1257,6 +1341,7 @@ fzw_status fzw_forward(fzw_plan* p, const float* nu, const float* bias, float* n
   }
   return guarded([&] {
     check_ready(p);
+    clear_flags(p);
     forward_all(p, nu, bias, nbar, logl);
     HIPCHK(hipGetLastError());
   });
@@ -1270,6 +1355,7 @@ fzw_status fzw_value_and_grad(fzw_plan* p, const float* nu, const float* bias, d
   }
   return guarded([&] {
     check_ready(p);
+    clear_flags(p);
     value_and_grad_all(p, nu, bias, logl, dnu, dbias);
     HIPCHK(hipGetLastError());
   });
@@ -1324,6 +1410,7 @@ static void enqueue_trajectory(fzw_plan* p, float* nu, float* u, float* p_nu, fl
   pa.epartial = p->epartial;
   pa.ne = p->R * 4;
   pa.nfree = p->nfree;
+  pa.flags = p->flags;
   const int C = p->n_chains;
   auto grad = [&] {
     launch_params(pa, C, 0, 0.f, kEBlk, nullptr, s);
@@ -1346,6 +1433,7 @@ static void enqueue_trajectory(fzw_plan* p, float* nu, float* u, float* p_nu, fl
     launch_params(pa, C, 3, 0.f, kEBlk, h, s);
   };
   const Scheme& sc = scheme_of(p->integrator);
+  clear_flags(p);   // a fill kernel, not a memset node, inside the captured graph
   auto kick = [&](double a) {
     for (auto& g : p->groups) launch_kick(leap(g), g.nc, (float)a, s);
     launch_params(pa, C, 1, (float)a, kEBlk, nullptr, s);
@@ -1553,7 +1641,10 @@ fzw_status fzw_bispectrum(fzw_plan* p, int mesh_n, const float* delta, double k1
       float* d[1] = {dst};
       zi(g, sp, d, 1, s);
     };
-    float *i1 = g.phi[0], *j1 = g.phi[1], *i2 = g.phi[2], *j2 = g.phi[3], *i3 = g.phi[4], *j3 = g.phi[5];
+    // six real scratch fields: the phi buffers, or the tensor buffers of a
+    // checkpointed plan
+    float* const* f6 = phi_buffers(p, g);
+    float *i1 = f6[0], *j1 = f6[1], *i2 = f6[2], *j2 = f6[3], *i3 = f6[4], *j3 = f6[5];
     shell_field(k1, false, i1);
     shell_field(k1, true, j1);
     shell_field(k2, false, i2);
@@ -1568,6 +1659,8 @@ fzw_status fzw_bispectrum(fzw_plan* p, int mesh_n, const float* delta, double k1
       launch_shell_power(g.spec[0], g.n, g.P, kf, k3[t] - 0.5 * dk, k3[t] + 0.5 * dk, partial, sc + 4 * t + 2, s);
     }
     launch_bispectrum_final(sc, p12, k3d, ntheta, g.n, g.box / g.n, out, s);
+    // the fields those buffers held
+    p->field_valid &= p->checkpoint ? ~(((1ull << (6 * p->W)) - 1ull) << 6) : ~1ull;
     HIPCHK(hipStreamSynchronize(s));   // k3 lives on the host stack
   });
 }
@@ -1623,11 +1716,16 @@ fzw_status fzw_set_integrator(fzw_plan* p, int kind) {
 }
 
 fzw_status fzw_get_field(fzw_plan* p, int chain, int field, float* out) {
-  if (!p || !out || chain < 0 || chain >= p->n_chains || field < 0 || field >= 6 + 6 * p->W) {
+  const bool known = field >= 0 && (field < 6 + 6 * (p ? p->W : 0) ||
+                                    (field >= FZW_FIELD_DRHO && field < FZW_FIELD_DPSI + 3));
+  if (!p || !out || chain < 0 || chain >= p->n_chains || !known) {
     g_last_error = "fzw_get_field: bad argument";
     return FZW_E_ARG;
   }
   return guarded([&] {
+    if (!((p->field_valid >> field) & 1ull))
+      throw Error(FZW_E_STATE, "fzw_get_field: field " + std::to_string(field) +
+                                   " was not left by the last evaluation (see fzw.h)");
     const Group& g = p->groups[p->chain_group[chain]];
     const long long o = (long long)(chain - g.c0) * g.nv;
     const size_t bytes = g.nv * sizeof(float);
@@ -1637,12 +1735,43 @@ fzw_status fzw_get_field(fzw_plan* p, int chain, int field, float* out) {
       launch_trace3(g.phi[0] + o, g.phi[1] + o, g.phi[2] + o, out, g.nv, p->stream);
       return;
     }
-    if (field <= 3) src = g.psi[field - 1] + o;
+    if (field == FZW_FIELD_DRHO) src = g.drho + o;
+    else if (field >= FZW_FIELD_DPSI) src = g.psi[field - FZW_FIELD_DPSI] + o;   // d Psi in place over Psi
+    else if (field <= 3) src = g.psi[field - 1] + o;
     else if (field == 4) src = g.rho + o;
     else if (field == 5) src = g.logf + o;
     else src = g.tens[field - 6] + o;
     HIPCHK(hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToDevice, p->stream));
   });
+}
+
+fzw_status fzw_nonfinite_flags(fzw_plan* p, int* flags) {
+  if (!p || !flags) {
+    g_last_error = "fzw_nonfinite_flags: bad argument";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    HIPCHK(hipMemcpyAsync(flags, p->flags, sizeof(int) * p->n_chains, hipMemcpyDeviceToDevice, p->stream));
+  });
+}
+
+fzw_status fzw_check_finite(fzw_plan* p, int* flags_host) {
+  if (!p) {
+    g_last_error = "fzw_check_finite: null plan";
+    return FZW_E_ARG;
+  }
+  int any = 0;
+  const fzw_status st = guarded([&] {
+    std::vector<int> f(p->n_chains, 0);
+    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPCHK(hipMemcpy(f.data(), p->flags, sizeof(int) * p->n_chains, hipMemcpyDeviceToHost));
+    for (int c = 0; c < p->n_chains; ++c) {
+      any |= f[c];
+      if (flags_host) flags_host[c] = f[c];
+    }
+  });
+  if (st != FZW_OK) return st;
+  return any ? FZW_W_NONFINITE : FZW_OK;
 }
 
 static fzw_status fft_common(fzw_plan* p, int n, int batch, const void* in, void* out, bool r2c) {

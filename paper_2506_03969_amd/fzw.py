@@ -20,6 +20,13 @@ _lib = None
 
 WEB_PHI, WEB_DELTA = 0, 1
 RSD_RADIAL = 3          # rsd_axis value: radial RSD about an observer at the box centre
+# get_field ids of the adjoint's cotangents (valid after a gradient evaluation)
+FIELD_DRHO = 18         # d logL / d rho
+FIELD_DPSI = 19         # d logL / d Psi_j is FIELD_DPSI + j
+# bits of the per-chain non-finite flags
+NF_STATE, NF_LOGL, NF_GRAD, NF_HAMILTONIAN = 1, 2, 4, 8
+W_NONFINITE = 1         # status of fzw_check_finite when some chain is flagged
+PLAN_CHECKPOINT = 1     # fzw_plan_create_ex flag: recompute phi_ij in the adjoint
 KERNEL_CLASSES = ("z_r2c", "z_c2r", "y_mix", "x_mix", "y_pure", "x_pure", "lpt_fwd", "lpt_bwd", "cic_deposit",
                   "cic_adjoint", "voxel_fwd", "likelihood", "voxel_bwd", "y_mix_multi", "x_mix_multi")
 # classes that are one kernel (template) each; the CIC deposit is a sequence
@@ -67,6 +74,9 @@ def load_library(path: str = _LIB_PATH):
     vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
     lib.fzw_plan_create.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(i), ctypes.POINTER(d),
                                     ctypes.POINTER(CCosmo), ctypes.POINTER(CWeb), vp]
+    lib.fzw_plan_create_ex.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(i), ctypes.POINTER(d),
+                                       ctypes.POINTER(CCosmo), ctypes.POINTER(CWeb), vp, ctypes.c_uint]
+    lib.fzw_plan_create_ex.restype = ctypes.c_int
     lib.fzw_plan_destroy.argtypes = [vp]
     lib.fzw_plan_destroy.restype = None
     lib.fzw_set_counts.argtypes = [vp, i, vp]
@@ -75,6 +85,10 @@ def load_library(path: str = _LIB_PATH):
     lib.fzw_set_sampling.argtypes = [vp, ctypes.POINTER(i), i, ctypes.POINTER(d), ctypes.POINTER(d)]
     lib.fzw_leapfrog.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i, vp, vp]
     lib.fzw_get_field.argtypes = [vp, i, i, vp]
+    lib.fzw_nonfinite_flags.argtypes = [vp, vp]
+    lib.fzw_nonfinite_flags.restype = ctypes.c_int
+    lib.fzw_check_finite.argtypes = [vp, ctypes.POINTER(i)]
+    lib.fzw_check_finite.restype = ctypes.c_int
     lib.fzw_fft_r2c.argtypes = [vp, i, i, vp, vp]
     lib.fzw_fft_c2r.argtypes = [vp, i, i, vp, vp]
     lib.fzw_set_cic_method.argtypes = [vp, i]
@@ -178,7 +192,9 @@ class Plan:
     """A set of chains (meshes) sharing cosmology and web settings."""
 
     def __init__(self, mesh_n: Sequence[int], box_l: Sequence[float], cosmo: CosmoParams, web: WebParams,
-                 device: int = 0):
+                 device: int = 0, checkpoint: bool = False):
+        """checkpoint: keep no first-order Hessian between the forward model and
+        the adjoint (recomputed from nu; FZW_PLAN_CHECKPOINT)."""
         lib = load_library()
         self.device = torch.device("cuda", device)
         self.mesh_n = [int(n) for n in mesh_n]
@@ -191,9 +207,9 @@ class Plan:
             arr_n = (ctypes.c_int * self.n_chains)(*self.mesh_n)
             arr_l = (ctypes.c_double * self.n_chains)(*self.box_l)
             cc, cw = cosmo.c(), web.c()
-            _check(lib.fzw_plan_create(ctypes.byref(h), self.n_chains, arr_n, arr_l, ctypes.byref(cc),
-                                       ctypes.byref(cw), ctypes.c_void_p(self.stream.cuda_stream)),
-                   "fzw_plan_create")
+            _check(lib.fzw_plan_create_ex(ctypes.byref(h), self.n_chains, arr_n, arr_l, ctypes.byref(cc),
+                                          ctypes.byref(cw), ctypes.c_void_p(self.stream.cuda_stream),
+                                          PLAN_CHECKPOINT if checkpoint else 0), "fzw_plan_create")
         self._h = h
         self.n_regions = lib.fzw_n_regions(h)
         self.offsets = [int(lib.fzw_chain_offset(h, c)) for c in range(self.n_chains)]
@@ -340,6 +356,21 @@ class Plan:
             out[name] = (ms.value, n.value, b.value)
         return out
 
+    def nonfinite_flags(self) -> torch.Tensor:
+        """Per-chain non-finite flags (NF_* bits) of the last evaluation call,
+        as an int32 device tensor (copied on the plan's stream)."""
+        out = torch.empty(self.n_chains, dtype=torch.int32, device=self.device)
+        _check(_lib.fzw_nonfinite_flags(self._h, _ptr(out, torch.int32)), "fzw_nonfinite_flags")
+        return out
+
+    def check_finite(self):
+        """(all finite, per-chain flags): synchronises the plan's stream."""
+        arr = (ctypes.c_int * self.n_chains)()
+        st = _lib.fzw_check_finite(self._h, arr)
+        if st < 0:
+            _check(st, "fzw_check_finite")
+        return st == 0, [int(x) for x in arr]
+
     def get_field(self, chain: int, field_id: int) -> torch.Tensor:
         n = self.mesh_n[chain]
         out = torch.empty((n, n, n), dtype=torch.float32, device=self.device)
@@ -416,11 +447,15 @@ class LogLikelihood(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
+        # chains are packed back to back whatever the shape of nu (flat, or
+        # [chains][N][N][N] when every chain has the same mesh): scale chain c's
+        # slice of the flat gradient by g[c]
         dnu, dbias = ctx.saved_tensors
         plan = ctx.plan
-        gn = torch.empty_like(dnu)
+        flat = dnu.reshape(-1)
+        gn = torch.empty_like(flat)
         for c in range(plan.n_chains):
             o, n = plan.offsets[c], plan.mesh_n[c] ** 3
-            gn[o:o + n] = dnu[o:o + n] * g[c].to(dnu.dtype)
-        gb = dbias * g.to(dbias.dtype).view(-1, *([1] * (dbias.dim() - 1)))
-        return gn, gb, None
+            gn[o:o + n] = flat[o:o + n] * g[c].to(dnu.dtype)
+        gb = (dbias.reshape(plan.n_chains, -1) * g.to(dbias.dtype).view(-1, 1)).view_as(dbias)
+        return gn.view_as(dnu), gb, None

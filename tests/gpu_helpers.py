@@ -6,7 +6,7 @@ import torch
 import fzw_inputs as fi
 
 
-def plan_for(w, chains=None):
+def plan_for(w, chains=None, checkpoint=False):
     from paper_2506_03969_amd import CosmoParams, Plan, WebParams
     c = w.cosmo
     cosmo = CosmoParams(c.omega_m, c.h, c.sigma8, c.n_s, c.d1, c.f_growth, c.r_s, c.rsd_axis, c.tau_sc,
@@ -14,7 +14,7 @@ def plan_for(w, chains=None):
     web = WebParams(tuple(w.web.kinds), tuple(w.web.smooth_r), tuple(w.web.ell), w.web.steepness,
                     w.web.lambda_th)
     chs = w.chains if chains is None else [w.chains[i] for i in chains]
-    return Plan([ch.n for ch in chs], [ch.box for ch in chs], cosmo, web)
+    return Plan([ch.n for ch in chs], [ch.box for ch in chs], cosmo, web, checkpoint=checkpoint)
 
 
 def dev(a, dtype=torch.float32):

@@ -19,7 +19,7 @@ import numpy as np
 import pytest
 
 import fzw_inputs as fi
-from tests.helpers import mock_case
+from tests.helpers import FIELD_TOL, GRAD_TOL, LOGL_TOL, Floor, fp32, mock_case, off_face, oracle_gradient
 
 torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
@@ -29,68 +29,136 @@ if not torch.cuda.is_available():  # pragma: no cover - collected on CPU hosts
 
 from tests.gpu_helpers import bias_entry_error, dev, dev_counts, host, plan_for, relnorm  # noqa: E402
 
-FIELD_TOL = 1e-5
-LOGL_TOL = 1e-4
-
-
 def _say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
 
 
-@pytest.mark.timeout(900)
-def test_c2_full_size_against_oracle():
-    """256^3, two webs, 16 regions, RSD: the bench workload."""
-    from oracle import model as om
-    om.set_workers(16)
-    _say("c2 256^3: mock data (oracle forward at truth)")
-    w, m, nu_t, nu_e, counts = mock_case("c2")
-    ch = w.chains[0]
-    nu = fi.near_truth_noise(ch)
-    p = plan_for(w)
-    p.set_counts(0, dev_counts(counts))
-    bias = dev(ch.bias.reshape(1, -1, 4))
-    logl, dnu, dbias = p.value_and_grad(dev(nu.ravel()), bias)
-    lf, nbar = p.forward(dev(nu.ravel()), bias, want_nbar=True)
-    gpu = {"dl": host(p.get_field(0, 0)), "rho": host(p.get_field(0, 4)),
-           "f": np.exp(host(p.get_field(0, 5)).ravel()), "nbar": host(nbar),
-           "psi": np.stack([host(p.get_field(0, k)) for k in (1, 2, 3)]),
-           "T": [np.stack([host(p.get_field(0, 6 + 6 * wi + k)) for k in range(6)]) for wi in range(2)]}
-    g_l, g_lf = float(host(logl)[0]), float(host(lf)[0])
-    g_dnu = host(dnu).reshape(nu.shape)
-    g_db = host(dbias).reshape(ch.bias.shape)
-    _say("c2 256^3: oracle forward")
-    st = m.forward(nu, ch.bias, counts)
+class _C2:
+    """The 256^3 two-web workload at a state near the data's noise, on the
+    same float32 inputs as the oracle; the GPU results are taken once, the
+    oracle's stages in the tests that use them (each test stays well under
+    three minutes on 16 host threads)."""
+
+    def __init__(self):
+        from oracle import model as om
+        from paper_2506_03969_amd import FIELD_DPSI, FIELD_DRHO
+        om.set_workers(16)
+        _say("c2 256^3: mock data (oracle forward at truth)")
+        w, m, nu_t, nu_e, counts = mock_case("c2")
+        ch = w.chains[0]
+        self.m, self.counts = m, counts
+        self.nu = fp32(fi.near_truth_noise(ch))
+        self.b = fp32(ch.bias)
+        p = plan_for(w)
+        p.set_counts(0, dev_counts(counts))
+        nu, bias = dev(self.nu.ravel()), dev(self.b[None])
+        logl, dnu, dbias = p.value_and_grad(nu, bias)
+        self.g = (float(host(logl)[0]), host(dnu).reshape(self.nu.shape), host(dbias).reshape(self.b.shape))
+        lf, nbar = p.forward(nu, bias, want_nbar=True)
+        self.g_lf = float(host(lf)[0])
+        self.fields = {"dl": host(p.get_field(0, 0)), "rho": host(p.get_field(0, 4)),
+                       "f": np.exp(host(p.get_field(0, 5)).ravel()), "nbar": host(nbar),
+                       "psi": np.stack([host(p.get_field(0, k)) for k in (1, 2, 3)]),
+                       "T": [np.stack([host(p.get_field(0, 6 + 6 * wi + k)) for k in range(6)]) for wi in range(2)]}
+        _say("c2 256^3: oracle forward")
+        self.st = m.forward(self.nu, self.b, counts)
+        # conditioned data: no tracer where the density is below 0.05 of the mean
+        cc = counts.copy().reshape(-1)
+        cc[self.st["x"] < 0.05] = 0
+        self.cc = cc.reshape(counts.shape)
+        p.set_counts(0, dev_counts(self.cc))
+        logl, dnu, dbias = p.value_and_grad(nu, bias)
+        self.gc = (float(host(logl)[0]), host(dnu).reshape(self.nu.shape), host(dbias).reshape(self.b.shape),
+                   host(p.get_field(0, FIELD_DRHO)), np.stack([host(p.get_field(0, FIELD_DPSI + j)) for j in range(3)]))
+        self.ref = None
+        self.refc = None
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return _C2()
+
+
+@pytest.mark.timeout(170)
+def test_c2_full_size_fields_and_logl(c2):
+    """256^3 (the bench workload): every forward intermediate within 1e-5
+    normwise of the oracle, logL within 1e-4, and forward and gradient calls
+    give the same logL bit for bit."""
+    gpu, st = c2.fields, c2.st
     errs = {"delta_L": relnorm(gpu["dl"], st["dl"]), "psi": relnorm(gpu["psi"], st["psi"]),
             "rho": relnorm(gpu["rho"], st["rho"]), "f": relnorm(gpu["f"], st["f"]),
             "nbar": relnorm(gpu["nbar"], st["nbar"])}
     for wi in range(2):
         errs["T%d" % wi] = relnorm(gpu["T"][wi], np.stack(st["tens"][wi]))
-    errs["logL"] = abs(g_l - st["logl"]) / abs(st["logl"])
+    errs["logL"] = abs(c2.g[0] - st["logl"]) / abs(st["logl"])
     _say("c2 256^3 fields:", " ".join("%s=%.2e" % kv for kv in errs.items()))
-    _say("c2 256^3: oracle adjoint")
-    ref_dnu, ref_db = m.adjoint(st)
-    e_nu = relnorm(g_dnu, ref_dnu)
-    e_bn = relnorm(g_db, ref_db)
-    e_b = bias_entry_error(g_db, ref_db)
-    _say("c2 256^3 gradient: dnu=%.2e dbias norm=%.2e entry=%.2e" % (e_nu, e_bn, e_b))
-    assert g_l == g_lf
+    c2.fields = None
+    assert c2.g[0] == c2.g_lf
     for k, v in errs.items():
         assert v < (LOGL_TOL if k == "logL" else FIELD_TOL), (k, v)
+
+
+@pytest.mark.timeout(170)
+def test_c2_full_size_gradient(c2):
+    """256^3, the mock data as drawn: the bias gradient within 1e-4 normwise
+    and per entry, d logL/d nu within 1e-4 or ten times the conditioning floor
+    (tracers in nearly empty cells, whose terms scale as 1/x^2, set it)."""
+    _say("c2 256^3: oracle adjoint")
+    ref_dnu, ref_db = c2.m.adjoint(c2.st)
+    _, g_dnu, g_db = c2.g
+    e_nu, e_bn, e_b = relnorm(g_dnu, ref_dnu), relnorm(g_db, ref_db), bias_entry_error(g_db, ref_db)
+    _say("c2 256^3 gradient, data as drawn: dnu=%.2e dbias norm=%.2e entry=%.2e" % (e_nu, e_bn, e_b))
     assert np.all(np.isfinite(g_dnu)) and np.all(np.isfinite(g_db))
-    assert e_bn < 1e-4 and e_b < 1e-4
-    if e_nu >= 1e-4:
-        # the oracle's own conditioning floor: how far its gradient moves when
-        # its input is rounded to FP32 or perturbed at relative 5e-7 (tracers
-        # in nearly empty cells next to CIC cell faces); held to ten times it
-        _say("c2 256^3: oracle conditioning floor")
-        rng = np.random.default_rng(99)
-        floor = 0.0
-        for x in (nu.astype(np.float32).astype(np.float64), nu * (1 + 5e-7 * rng.standard_normal(nu.shape))):
-            _, gx, _ = m.value_and_grad(x, ch.bias, counts)
-            floor = max(floor, relnorm(gx, ref_dnu))
-            _say("c2 256^3: floor sample %.2e" % relnorm(gx, ref_dnu))
-        assert e_nu < 10 * floor, (e_nu, floor)
+    assert e_bn < GRAD_TOL and e_b < GRAD_TOL
+    fl = Floor(c2.m, c2.nu, c2.b, c2.counts, ref_dnu, ref_db, c2.st["dbias_abs"])
+    ok = fl.holds_nu(e_nu)
+    _say("c2 256^3 floor, data as drawn (%d draws): nu %.2e" % (fl.draws, fl.nu_f))
+    c2.st = None
+    assert ok
+
+
+@pytest.mark.timeout(170)
+def test_c2_full_size_conditioned_cotangents(c2):
+    """256^3, conditioned data (those tracers removed): d logL/d rho (every
+    voxel) and d logL/d Psi (particles more than 1e-5 cells from every cell
+    face) at the fixed 1e-4, logL 1e-4, bias gradient 1e-4 normwise; d logL/d
+    nu within 1e-4 or ten times the floor (about a thousand particles lie
+    within float32 noise of a cell face at this size)."""
+    _say("c2 256^3: oracle on the conditioned data (%d tracers removed)" % int(c2.counts.sum() - c2.cc.sum()))
+    st = c2.m.forward(c2.nu, c2.b, c2.cc)
+    ref_dnu, ref_db = c2.m.adjoint(st)
+    fl = Floor(c2.m, c2.nu, c2.b, c2.cc, ref_dnu, ref_db, st["dbias_abs"])
+    c2.refc = fl
+    g_l, g_dnu, g_db, g_drho, g_dpsi = c2.gc
+    keep = off_face(st["pos"])
+    e = {"logL": abs(g_l - st["logl"]) / abs(st["logl"]), "dnu": relnorm(g_dnu, ref_dnu),
+         "drho": relnorm(g_drho, st["drho"]),
+         "dpsi_off_face": relnorm(g_dpsi.reshape(3, -1)[:, keep], st["dpsi"].reshape(3, -1)[:, keep]),
+         "dbias": relnorm(g_db, ref_db), "dbias_entry": bias_entry_error(g_db, ref_db)}
+    _say("c2 256^3 conditioned (%d particles near a face):" % int((~keep).sum()),
+         " ".join("%s=%.2e" % kv for kv in e.items()))
+    assert e["logL"] < LOGL_TOL
+    assert e["drho"] < GRAD_TOL and e["dpsi_off_face"] < GRAD_TOL
+    assert e["dbias"] < GRAD_TOL
+    del st
+    ok = fl.holds_nu(e["dnu"])
+    _say("c2 256^3 conditioned d/dnu floor (%d draws): %.2e" % (fl.draws, fl.nu_f))
+    assert ok
+
+
+@pytest.mark.timeout(170)
+def test_c2_full_size_conditioned_bias_entries(c2):
+    """256^3, conditioned data: each bias-table entry within 1e-4 or ten times
+    the conditioning floor (entries whose voxel sums cancel)."""
+    if c2.refc is None:
+        pytest.skip("needs test_c2_full_size_conditioned_cotangents")
+    fl = c2.refc
+    g_db = c2.gc[2]
+    e_b = bias_entry_error(g_db, fl.args[5])
+    fl_ok = fl.holds_bias(g_db)
+    _say("c2 256^3 conditioned bias entries %.2e (floor %d draws: %.2e)" % (e_b, fl.draws, fl.bias_f))
+    assert fl_ok
 
 
 def _ragged():
@@ -110,24 +178,29 @@ def test_ragged_batch_against_oracle():
     for c in sel:
         _say("ragged: mock data for chain", c, "n =", w.chains[c].n)
         ww, m, nu_t, nu_e, counts = mock_case("c3", None, None, c)
-        cases.append((ww.chains[c], m, fi.near_truth_noise(ww.chains[c]), counts))
+        ch = ww.chains[c]
+        cases.append((ch, m, fp32(fi.near_truth_noise(ch)), counts, fp32(ch.bias)))
     p = plan_for(w, sel)
-    for i, (ch, m, nu, counts) in enumerate(cases):
+    for i, (ch, m, nu, counts, b) in enumerate(cases):
         p.set_counts(i, dev_counts(counts))
-    nu_all = dev(np.concatenate([nu.ravel() for _, _, nu, _ in cases]))
-    bias_all = dev(np.stack([ch.bias for ch, _, _, _ in cases]))
+    nu_all = dev(np.concatenate([nu.ravel() for _, _, nu, _, _ in cases]))
+    bias_all = dev(np.stack([b for _, _, _, _, b in cases]))
     logl, dnu, dbias = p.value_and_grad(nu_all, bias_all)
     gl, gd, gb = host(logl), host(dnu), host(dbias)
-    for i, (ch, m, nu, counts) in enumerate(cases):
-        ref_l, ref_dnu, ref_db = m.value_and_grad(nu, ch.bias, counts)
+    for i, (ch, m, nu, counts, b) in enumerate(cases):
+        ref_l, ref_dnu, ref_db, st = oracle_gradient(m, nu, b, counts)
         o = p.offsets[i]
         g = gd[o:o + ch.n ** 3].reshape(nu.shape)
         e_l = abs(gl[i] - ref_l) / abs(ref_l)
         e_nu = relnorm(g, ref_dnu)
         e_bn = relnorm(gb[i], ref_db)
-        _say("ragged chain n=%d: logL=%.2e dnu=%.2e dbias norm=%.2e" % (ch.n, e_l, e_nu, e_bn))
+        e_b = bias_entry_error(gb[i], ref_db)
+        fl = Floor(m, nu, b, counts, ref_dnu, ref_db, st["dbias_abs"])
+        ok_nu, ok_b = fl.holds_nu(e_nu), fl.holds_bias(gb[i])
+        _say("ragged chain n=%d: logL=%.2e dnu=%.2e dbias norm=%.2e entry=%.2e (floor %d draws: nu %.2e bias %.2e)"
+             % (ch.n, e_l, e_nu, e_bn, e_b, fl.draws, fl.nu_f, fl.bias_f))
         assert e_l < LOGL_TOL
-        assert e_nu < 1e-3 and e_bn < 1e-3
+        assert e_bn < GRAD_TOL and ok_nu and ok_b
 
 
 @pytest.mark.timeout(600)

@@ -5,7 +5,7 @@ import pytest
 
 import fzw_inputs as fi
 from oracle import hmc
-from tests.helpers import mock_case
+from tests.helpers import fp32, mock_case
 
 torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
@@ -37,12 +37,13 @@ def _tie(w):
 def _setup(name, n):
     w, m, nu_t, nu_e, counts = mock_case(name, n)
     ch = w.chains[0]
-    nu = fi.near_truth_noise(ch)
+    # every input as the float32 values the GPU is handed
+    nu = fp32(fi.near_truth_noise(ch))
     mu, sig = _priors(w)
-    u0 = np.log(np.array([ch.bias[r[0], c] for r, c in w.free]))
+    u0 = fp32(np.log(np.array([ch.bias[r[0], c] for r, c in w.free])))
     g = fi.rng_for(ch, fi.ROLE_MOMENTUM)
-    p_nu = g.standard_normal(nu.shape)
-    p_u = g.standard_normal(u0.shape)
+    p_nu = fp32(g.standard_normal(nu.shape))
+    p_u = fp32(g.standard_normal(u0.shape))
     return w, m, counts, nu, u0, p_nu, p_u, mu, sig
 
 
@@ -54,9 +55,10 @@ def test_leapfrog_matches_oracle(case, scheme):
     name, n = case
     w, m, counts, nu, u0, p_nu, p_u, mu, sig = _setup(name, n)
     ch = w.chains[0]
-    eps, steps = 2e-3, 4
-    minv_u = np.full(u0.shape, 1e-2)
-    gfn = lambda q, u: hmc.potential_and_grad(m, q, u, ch.bias, w.free, mu, sig, counts)
+    eps, steps = float(fp32(2e-3)), 4
+    minv_u = fp32(np.full(u0.shape, 1e-2))
+    bias = fp32(ch.bias)
+    gfn = lambda q, u: hmc.potential_and_grad(m, q, u, bias, w.free, mu, sig, counts)
     q1, u1, p1, pu1, h0, h1 = hmc.integrate(gfn, nu, u0, p_nu, p_u, 1.0, minv_u, eps, steps, scheme)
 
     plan = plan_for(w)
@@ -65,7 +67,7 @@ def test_leapfrog_matches_oracle(case, scheme):
     plan.set_integrator(scheme)
     t_nu, t_u = dev(nu.ravel()), dev(u0[None])
     t_p, t_pu = dev(p_nu.ravel()), dev(p_u[None])
-    base = dev(ch.bias[None])
+    base = dev(bias[None])
     minv = torch.ones_like(t_nu)
     t_minv_u = dev(minv_u[None])
     step = dev(np.array([eps]))
@@ -117,15 +119,16 @@ def test_leapfrog_full_signed_table_matches_oracle():
     ch = w.chains[0]
     wf = dataclasses.replace(w, free=fi.full_table_free(w.n_regions))
     mu, sig = fi.prior_arrays(wf)
-    u0 = fi.free_start(wf, ch)
+    u0 = fp32(fi.free_start(wf, ch))
     signs = fi.free_signs(wf, ch)
-    nu = fi.near_truth_noise(ch)
+    nu = fp32(fi.near_truth_noise(ch))
     g = fi.rng_for(ch, fi.ROLE_MOMENTUM)
-    p_nu = g.standard_normal(nu.shape)
-    p_u = g.standard_normal(u0.shape)
-    eps, steps = 2e-3, 4
-    minv_u = np.full(u0.shape, 1e-3)
-    gfn = lambda q, u: hmc.potential_and_grad(m, q, u, ch.bias, wf.free, mu, sig, counts, signs)
+    p_nu = fp32(g.standard_normal(nu.shape))
+    p_u = fp32(g.standard_normal(u0.shape))
+    eps, steps = float(fp32(2e-3)), 4
+    minv_u = fp32(np.full(u0.shape, 1e-3))
+    bias = fp32(ch.bias)
+    gfn = lambda q, u: hmc.potential_and_grad(m, q, u, bias, wf.free, mu, sig, counts, signs)
     q1, u1, p1, pu1, h0, h1 = hmc.leapfrog(gfn, nu, u0, p_nu, p_u, 1.0, minv_u, eps, steps)
     plan = plan_for(wf)
     plan.set_counts(0, dev_counts(counts))
@@ -133,7 +136,7 @@ def test_leapfrog_full_signed_table_matches_oracle():
     plan.set_sampling_signs(signs)
     t_nu, t_u = dev(nu.ravel()), dev(u0[None])
     t_p, t_pu = dev(p_nu.ravel()), dev(p_u[None])
-    hs, he = plan.leapfrog(t_nu, t_u, t_p, t_pu, dev(ch.bias[None]), torch.ones_like(t_nu), dev(minv_u[None]),
+    hs, he = plan.leapfrog(t_nu, t_u, t_p, t_pu, dev(bias[None]), torch.ones_like(t_nu), dev(minv_u[None]),
                            dev(np.array([eps])), steps)
     g_h0, g_h1 = float(host(hs)[0]), float(host(he)[0])
     e_q = relnorm(host(t_nu).reshape(nu.shape) - nu, q1 - nu)
