@@ -288,6 +288,21 @@ fzw_status fzw_power_multipoles(fzw_plan* plan, int mesh_n, const float* a, cons
 fzw_status fzw_bispectrum(fzw_plan* plan, int mesh_n, const float* delta, double k1, double k2, double dk,
                           int ntheta, const double* theta, double* out);
 
+/* fzw_power_multipoles for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, same kernels and the same results bit for bit,
+ * but the call allocates nothing.  Its workgroups' partial sums go to a fixed
+ * device array of 4 MiB per GPU (512 workgroups x 256 bins x 4 float64),
+ * held by the library until the process ends, whose address is resolved when
+ * the first plan is created on that GPU; the transforms use the plan's own
+ * workspace.  nbins <= 256 (FZW_E_ARG above).  Every call on one GPU shares
+ * that array and every partial is written before it is read, so nothing
+ * needs clearing; calls that overlap on one GPU (other streams or threads,
+ * other plans) race on it and must be serialised by the caller.  No timing
+ * records are made (fzw_timing_enable does not apply). */
+fzw_status fzw_power_multipoles_noalloc(fzw_plan* plan, int mesh_n, const float* a, const float* b, double k_lo,
+                                        double dk, int nbins, double* out);
+
 /* Splitting scheme of fzw_leapfrog's steps (Section 2.2 names second- and
  * fourth-order HMC and the variant of Blanes, Casas & Sanz-Serna 2014).  One
  * step with step size eps is K(a_0) D(b_1) K(a_1) ... D(b_m) K(a_m), K(a) the

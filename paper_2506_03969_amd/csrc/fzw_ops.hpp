@@ -233,6 +233,13 @@ void launch_wiener_contrast(const uint16_t* counts, const double* scal, int chai
 void launch_wiener_filter(float2* spec, const float* htab, int n, int pitch, const double* scal, int chain0,
                           int chains, long long per_chain, hipStream_t s);
 int stats_blocks();
+// The multipoles' fixed partials array of the allocation-free call: its
+// device address is resolved once per device (with that device current) by
+// scratch_setup; scratch_ptr returns it (nullptr before).  At most
+// scratch_max_bins() bins.
+hipError_t scratch_setup(int device);
+double* scratch_ptr(int device);
+int scratch_max_bins();
 void launch_multipoles(const float2* a, const float2* b, int n, int pitch, double kf, double k_lo, double dk,
                        int nbins, double pnorm, double* partial, double* out, hipStream_t s);
 void launch_shell(const float2* src, float2* dst, int n, int pitch, double kf, double lo, double hi, hipStream_t s);

@@ -125,6 +125,7 @@ using namespace fzw;
 
 struct fzw_plan {
   int n_chains = 0;
+  int device = 0;                     // the device current at fzw_plan_create
   // FZW_PLAN_CHECKPOINT: phi_ij is not kept between the forward model and the
   // adjoint, which recomputes it from nu (no phi buffers in the workspace)
   bool checkpoint = false;
@@ -1265,6 +1266,10 @@ fzw_status fzw_plan_create_ex(fzw_plan** out, int n_chains, const int* mesh_n, c
     }
     p->total_vox = off;
     p->counts_set.assign(n_chains, false);
+    // (arguments are validated above, before any device call)
+    HIPCHK(hipGetDevice(&p->device));
+    // the fixed partials array of fzw_power_multipoles_noalloc on this device
+    HIPCHK(scratch_setup(p->device));
     size_t part = 0;
     for (auto& g : p->groups) {
       build_tables(p, g);
@@ -1602,6 +1607,34 @@ fzw_status fzw_power_multipoles(fzw_plan* p, int mesh_n, const float* a, const f
     Group g = stats_group(p, mesh_n);
     hipStream_t s = p->stream;
     double* buf = stats_buffer(p);
+    forward_spectrum(g, a, g.spec[0], s);
+    if (b) forward_spectrum(g, b, g.spec[1], s);
+    const double dx = g.box / g.n;
+    const double pnorm = dx * dx * dx / ((double)g.n * g.n * g.n);
+    launch_multipoles(g.spec[0], b ? g.spec[1] : g.spec[0], g.n, g.P, 2.0 * M_PI / g.box, k_lo, dk, nbins, pnorm,
+                      buf, out, s);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+fzw_status fzw_power_multipoles_noalloc(fzw_plan* p, int mesh_n, const float* a, const float* b, double k_lo,
+                                        double dk, int nbins, double* out) {
+  if (!p || !a || !out || !(dk > 0) || nbins < 1) {
+    g_last_error = "fzw_power_multipoles_noalloc: bad argument";
+    return FZW_E_ARG;
+  }
+  if (nbins > scratch_max_bins()) {
+    g_last_error = "fzw_power_multipoles_noalloc: nbins " + std::to_string(nbins) + " exceeds the fixed partials " +
+                   "array (at most " + std::to_string(scratch_max_bins()) + " bins)";
+    return FZW_E_ARG;
+  }
+  return guarded([&] {
+    double* buf = scratch_ptr(p->device);
+    if (!buf) throw Error(FZW_E_STATE, "fzw_power_multipoles_noalloc: partials array not set up on this device");
+    // no timing records: they would create events
+    t_plan = nullptr;
+    Group g = stats_group(p, mesh_n);
+    hipStream_t s = p->stream;
     forward_spectrum(g, a, g.spec[0], s);
     if (b) forward_spectrum(g, b, g.spec[1], s);
     const double dx = g.box / g.n;

@@ -9,6 +9,8 @@
 // shell decisions use the same FP64 arithmetic, in the same order, as the
 // plain definition (|k| = sqrt(kx^2 + ky^2 + kz^2) with k_a = kf n_a, then
 // floor((|k| - k_lo) / dk)); contraction into fma is off there.
+#include <mutex>
+
 #include "fzw_device.hpp"
 #include "fzw_ops.hpp"
 
@@ -196,6 +198,43 @@ __global__ void bispectrum_final_kernel(const double* __restrict__ sc, const dou
 }  // namespace
 
 int stats_blocks() { return 512; }
+
+// Block partials of the allocation-free multipoles call
+// (fzw_power_multipoles_noalloc): a fixed array per GPU, held until the
+// process ends, instead of a buffer allocated at the first call.  Host code
+// never uses the array's name as an address (on the host it is only a
+// stand-in): scratch_setup resolves the device address once per device, and
+// every launch takes that pointer.
+constexpr int kScratchBins = 256;
+constexpr size_t kScratchDoubles = (size_t)512 * kScratchBins * 4;   // stats_blocks() x bins x 4: 4 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_max_bins() { return kScratchBins; }
+
+hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (cur != device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = static_cast<double*>(ptr);
+  return hipSuccess;
+}
+
+double* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 void launch_multipoles(const float2* a, const float2* b, int n, int pitch, double kf, double k_lo, double dk,
                        int nbins, double pnorm, double* partial, double* out, hipStream_t s) {

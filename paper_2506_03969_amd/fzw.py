@@ -115,6 +115,8 @@ def load_library(path: str = _LIB_PATH):
     lib.fzw_set_sampling_signs.argtypes = [vp, ctypes.POINTER(i), i]
     lib.fzw_power_multipoles.argtypes = [vp, i, vp, vp, d, d, i, vp]
     lib.fzw_bispectrum.argtypes = [vp, i, vp, d, d, d, i, ctypes.POINTER(d), vp]
+    lib.fzw_power_multipoles_noalloc.argtypes = [vp, i, vp, vp, d, d, i, vp]
+    lib.fzw_power_multipoles_noalloc.restype = ctypes.c_int
     lib.fzw_inverse_mass.argtypes = [vp, vp, vp, ll, i]
     lib.fzw_dual_avg_init.argtypes = [ctypes.POINTER(CDualAvg), d, d]
     lib.fzw_dual_avg_init.restype = None
@@ -309,6 +311,18 @@ class Plan:
         _check(_lib.fzw_power_multipoles(self._h, int(n), _ptr(a, torch.float32), _ptr(b, torch.float32),
                                          float(k_lo), float(dk), int(nbins), _ptr(out, torch.float64)),
                "fzw_power_multipoles")
+        return out
+
+    def power_multipoles_noalloc(self, a, b=None, k_lo=0.0, dk=None, nbins=32, mesh_n=None, out=None):
+        """power_multipoles through the library's allocation-free entry point
+        (its partials live in a fixed device array); `out` may be passed so
+        that nothing is allocated on this side either."""
+        n = mesh_n or round(a.numel() ** (1.0 / 3.0))
+        if out is None:
+            out = torch.empty((nbins, 4), dtype=torch.float64, device=self.device)
+        _check(_lib.fzw_power_multipoles_noalloc(self._h, int(n), _ptr(a, torch.float32), _ptr(b, torch.float32),
+                                                 float(k_lo), float(dk), int(nbins), _ptr(out, torch.float64)),
+               "fzw_power_multipoles_noalloc")
         return out
 
     def bispectrum(self, delta, k1, k2, dk, thetas, mesh_n=None):
