@@ -196,17 +196,6 @@ __global__ __launch_bounds__(kThreadsXY) void xy_pass_kernel(PassArgs a, const f
         }
       }
     }
-    // the radial table shared by inputs 0..i, applied once to their sum
-    if (i == a.post_after) {
-#pragma unroll
-      for (int j = 0; j < E; ++j) {
-        const int nr = freq_index(r0 + j * RS, N);
-        const int n0 = AXIS == 0 ? nr : 0, n1 = AXIS == 0 ? nb : nr;
-        const float r = radial_value(a.rf, a.post_tab, n0 * n0 + n1 * n1 + nz * nz, a.tabs, a.tab_stride);
-#pragma unroll
-        for (int m = 0; m < NMID; ++m) mid[m][j] = cscale(mid[m][j], r);
-      }
-    }
   }
 
   for (int o = 0; o < a.nout; ++o) {
@@ -607,19 +596,6 @@ __global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1, 3) void xy4_pass_kernel(
         kv.n[2] = nz;
         kv.n2 = kv.n[0] * kv.n[0] + kv.n[1] * kv.n[1] + nz * nz;
         mid[m][e] = cadd(mid[m][e], cmul(spec_eval<!PF>(op, kv, a.kf, nyq, a.tabs, a.tab_stride, a.rf), val[e]));
-      }
-    }
-    // the radial table shared by inputs 0..i, applied once to their sum
-    if (i == a.post_after) {
-#pragma unroll
-      for (int e = 0; e < N2; ++e) {
-        const int nr = freq_index(rowB(e), N);
-        const int n0 = AXIS == 0 ? nr : 0, n1 = AXIS == 0 ? nb : nr;
-        const int q = n0 * n0 + n1 * n1 + nz * nz;
-        const float r = PF ? a.tabs[a.post_tab * a.tab_stride + min(q, a.tab_stride - 1)]
-                           : radial_value(a.rf, a.post_tab, q, a.tabs, a.tab_stride);
-#pragma unroll
-        for (int m = 0; m < NMID; ++m) mid[m][e] = cscale(mid[m][e], r);
       }
     }
   }

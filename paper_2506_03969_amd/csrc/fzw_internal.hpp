@@ -56,10 +56,6 @@ struct PassArgs {
   int tab_stride;
   float kf;                   // 2 pi / L
   const RadialForms* rf;      // tables evaluated in closed form instead of looked up (device)
-  // inputs 0..post_after carry no radial factor of their own: mid is
-  // multiplied by radial table post_tab once, after input post_after (-1:
-  // never), instead of gathering the table for each of them
-  int post_after, post_tab;
 };
 
 // The z transforms around the LPT pointwise step, fused with it (see

@@ -378,15 +378,6 @@ struct Pass {
       for (auto& o : r) o = spec_zero();
     for (auto& r : a.B)
       for (auto& o : r) o = spec_zero();
-    a.post_after = -1;
-    a.post_tab = 0;
-  }
-  // inputs 0..after (given without a radial factor) share radial table tab:
-  // the pass multiplies their sum by it once
-  Pass& post(int after, int tab) {
-    a.post_after = after;
-    a.post_tab = tab;
-    return *this;
   }
   Pass& in(const float2* p, bool fft) {
     a.in_fft |= fft ? (1u << a.nin) : 0u;
@@ -600,12 +591,11 @@ void forward_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
   // ALPT blend -> Psi (Section 2.3)
   {
     pure_pass(g, Y, false, &sp[2], 2, s);
-    // the S2 and delta_L inputs share K/k^2: applied once to their sum
     Pass ps;
-    ps.in(sp[2], true).in(sp[1], false).in(sp[3], true).post(1, TAB_K_INVK2);
-    ps.a.A[0][0] = spec_const((float)(3.0 / 7.0) * d1 * d1 * invn3);
-    ps.a.A[0][1] = spec_const(d1 * invn3);
-    ps.a.A[0][2] = spec(-invn3, 0.f, NONE, NONE, TAB_1MK_INVK2, NONE);
+    ps.in(sp[2], true).in(sp[3], true).in(sp[1], false);
+    ps.a.A[0][0] = spec((float)(3.0 / 7.0) * d1 * d1 * invn3, 0.f, NONE, NONE, TAB_K_INVK2, NONE);
+    ps.a.A[0][1] = spec(-invn3, 0.f, NONE, NONE, TAB_1MK_INVK2, NONE);
+    ps.a.A[0][2] = spec(d1 * invn3, 0.f, NONE, NONE, TAB_K_INVK2, NONE);
     ps.out(sp[4], true).out(sp[5], true);
     ps.a.B[0][0] = spec(0.f, 1.f, X, NONE, NONE, NONE);  // i k_x
     ps.a.B[1][0] = spec_const(1.f);
@@ -758,15 +748,12 @@ void adjoint_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
     zf(g, dd, &sp[12], 1, s);
     for (int w = 0; w < W; ++w) hessian_yf(g, &sp[6 * w], sp[6 * w + 0], sp[6 * w + 1], sp[6 * w + 2], s);
     pure_pass(g, Y, false, &sp[12], 1, s);
-    // web 0's three inputs share its radial multiplier: applied once to their sum
     Pass ps;
-    ps.post(2, TAB_WEB0);
     for (int w = 0; w < W; ++w) {
-      const int tb = w == 0 ? NONE : TAB_WEB0 + w;
       ps.in(sp[6 * w + 0], true).in(sp[6 * w + 1], true).in(sp[6 * w + 2], true);
-      ps.a.A[0][3 * w + 0] = spec(invn3, 0.f, X, X, tb, NONE);
-      ps.a.A[0][3 * w + 1] = spec(invn3, 0.f, X, NONE, tb, NONE);
-      ps.a.A[0][3 * w + 2] = spec(invn3, 0.f, NONE, NONE, tb, NONE);
+      ps.a.A[0][3 * w + 0] = spec(invn3, 0.f, X, X, TAB_WEB0 + w, NONE);
+      ps.a.A[0][3 * w + 1] = spec(invn3, 0.f, X, NONE, TAB_WEB0 + w, NONE);
+      ps.a.A[0][3 * w + 2] = spec(invn3, 0.f, NONE, NONE, TAB_WEB0 + w, NONE);
     }
     ps.in(sp[12], true);
     ps.a.A[0][3 * W] = spec_const(invn3);
@@ -810,9 +797,9 @@ void adjoint_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
       run_pass(g, Y, pyz, 1, s);
     }
     Pass ps;
-    ps.in(sp[0], true).in(sp[1], true).post(1, TAB_INVK2);   // both share 1/k^2
-    ps.a.A[0][0] = spec(0.f, -1.f, X, NONE, NONE, NONE);
-    ps.a.A[0][1] = spec_const(1.f);
+    ps.in(sp[0], true).in(sp[1], true);
+    ps.a.A[0][0] = spec(0.f, -1.f, X, NONE, TAB_INVK2, NONE);
+    ps.a.A[0][1] = spec(1.f, 0.f, NONE, NONE, TAB_INVK2, NONE);
     ps.out(sp[2], true).out(sp[3], true).out(sp[4], false);
     ps.a.B[0][0] = spec((float)(3.0 / 7.0) * d1 * d1 * invn3, 0.f, NONE, NONE, TAB_K, NONE);
     ps.a.B[1][0] = spec(-invn3, 0.f, NONE, NONE, TAB_1MK, NONE);
@@ -847,10 +834,10 @@ void adjoint_group(fzw_plan* p, Group& g, const float* nu, const float* bias, fl
   {
     hessian_yf(g, &sp[5], sp[5], sp[6], sp[7], s);
     Pass ps;
-    ps.in(sp[5], true).in(sp[6], true).in(sp[7], true).in(sp[4], false).post(2, TAB_H_INVK2);   // share h/k^2
-    ps.a.A[0][0] = spec(invn3, 0.f, X, X, NONE, NONE);
-    ps.a.A[0][1] = spec(invn3, 0.f, X, NONE, NONE, NONE);
-    ps.a.A[0][2] = spec_const(invn3);
+    ps.in(sp[5], true).in(sp[6], true).in(sp[7], true).in(sp[4], false);
+    ps.a.A[0][0] = spec(invn3, 0.f, X, X, TAB_H_INVK2, NONE);
+    ps.a.A[0][1] = spec(invn3, 0.f, X, NONE, TAB_H_INVK2, NONE);
+    ps.a.A[0][2] = spec(invn3, 0.f, NONE, NONE, TAB_H_INVK2, NONE);
     ps.a.A[0][3] = spec_const(invn3);
     ps.out(sp[0], true);
     ps.a.B[0][0] = spec_const(1.f);
