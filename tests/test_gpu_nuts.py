@@ -5,12 +5,18 @@ batches against single chains, and the warm-up helpers.
 A transition is a chain of random and sign decisions taken on energies and
 momentum sums that the FP32 path and the FP64 oracle compute with different
 rounding.  For every draw the oracle reports how far its closest decision
-was from flipping, and it is also run with its gradients perturbed at
-relative 1e-6 (the size of the FP32 path's gradient error).  Draws whose
-closest decision is nearer than the two paths' expected difference (1e-3 in
-probability, 1e-3 relative in a U-turn dot product), or whose perturbed
-oracle runs disagree on the tree, are not compared; the test needs at least
-three compared draws per case.  Compared: the tree depth, the leapfrog steps
+was from flipping, and it is also run three times with its gradients
+perturbed at relative 1e-6 (the size of the FP32 path's gradient error) and
+its particle positions at relative 2^-23 (the rounding of a position held in
+float32).  The second matters on long trajectories: where a particle sits
+within that rounding of a cell face at some leaf, the two paths may put it on
+different sides, its cloud-in-cell derivative jumps, and the rest of the
+trajectory can end elsewhere (a depth-7 tree at 16^3 passes such states at
+most leaves).  Draws whose closest decision is nearer than the two paths'
+expected difference (1e-3 in probability, 1e-3 relative in a U-turn dot
+product), or whose perturbed oracle runs disagree on the tree or on the
+potential of the new state, are not compared; the test needs at least three
+compared draws per case.  Compared: the tree depth, the leapfrog steps
 and the divergence flag exactly; the potential at the new state within 1e-5;
 the acceptance statistic within 5e-3 plus the spread of the perturbed oracle
 runs (a leaf whose energy sits on a steep stretch of the potential, such as a
@@ -20,6 +26,7 @@ the rest of the trajectory at the 1e-4 level, which moves it by a few 1e-3);
 the displacement of
 the new state within 1e-3 normwise (bit-exact when the start point is
 kept)."""
+import copy
 import dataclasses
 
 import numpy as np
@@ -46,11 +53,30 @@ def _draws(ch, seed, size, md):
     return z, uni
 
 
+def _jittered(m, rng, rel):
+    """A copy of the oracle model whose particle positions carry a fresh
+    uniform error of up to `rel` relative (at least `rel` cells) at every
+    evaluation."""
+    mj = copy.copy(m)
+
+    def positions(psi):
+        pos = type(m).positions(mj, psi)
+        return pos + rel * np.maximum(np.abs(pos), 1.0) * rng.uniform(-1.0, 1.0, pos.shape)
+    mj.positions = positions
+    return mj
+
+
+POS_JITTER = 2.0 ** -23
+
+
 def _oracle_potential(m, w, ch, mu, sig, counts, shape, noise=0.0, seed=0):
     """Potential and gradient of the oracle; with `noise`, the gradient is
-    perturbed at that relative size (seeded)."""
+    perturbed at that relative size and the particle positions at relative
+    POS_JITTER (seeded)."""
     nv = int(np.prod(shape))
     rng = np.random.default_rng(seed)
+    if noise:
+        m = _jittered(m, rng, POS_JITTER)
 
     def pg(q):
         pot, gnu, gu = hmc.potential_and_grad(m, q[:nv].reshape(shape), q[nv:], ch.bias, w.free, mu, sig, counts)
@@ -66,7 +92,7 @@ def _oracle_potential(m, w, ch, mu, sig, counts, shape, noise=0.0, seed=0):
 # model.  Steps near the stability limit of the stiffest modes (0.1 here)
 # make the trajectory itself chaotic: a 1e-6 change of the gradient then
 # moves late leaves' energies by O(1), so they are not used.
-CASES = [("c0fd", None, 0.03, 4, 12, "leapfrog"), ("c0fd", None, 0.04, 8, 4, "leapfrog"),
+CASES = [("c0fd", None, 0.03, 4, 12, "leapfrog"), ("c0fd", None, 0.04, 8, 12, "leapfrog"),
          ("c0fd", None, 0.3, 5, 8, "leapfrog"), ("c2", 32, 0.004, 4, 6, "leapfrog"),
          ("c0fd", None, 0.05, 4, 8, "blanes2"), ("c0fd", None, 0.05, 4, 6, "yoshida4")]
 
