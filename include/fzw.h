@@ -374,7 +374,12 @@ fzw_status fzw_set_cic_method(fzw_plan* plan, int method);
  * for pure x/y transforms -- and keeps the four-step kernels unless the
  * alternative is at least 10% faster.  Every later plan of that size uses the
  * same kernels, so results of plans in one process are comparable bit for
- * bit.  The environment variable FZW_FFT_TUNE=0 keeps the defaults.
+ * bit.  Two processes may choose differently where the two families' times
+ * lie within timing noise of the 10% margin (small meshes: 7.7 against
+ * 8.3 us for the 16^3 z passes), and their float32 results then differ by
+ * rounding.  The environment variable FZW_FFT_TUNE=0 keeps the defaults, and
+ * fzw_set_fft_schedule fixes a choice: either makes results reproducible
+ * bit for bit across processes.
  *   z, xy, pure: the chosen family per pass type (0 or 1);
  *   us6 (nullable): measured microseconds per launch, [z, xy, pure] x
  *     [four-step, alternative] (0 where a family does not exist for the size).

@@ -6,10 +6,13 @@ configuration the benchmark times.
 * Ragged batch (one 64^3, one 96^3 and one 128^3 chain in one plan, as in the
   32-chain workload): every chain against the oracle, and a batched leapfrog
   trajectory equal bit for bit to the per-chain trajectories.
-* 512^3: too large for the oracle, so properties that hold at any size: the
-  transform against numpy, mass conservation of the deposit, determinism,
-  agreement of the two likelihood paths, and central differences of the
-  FP64-reduced logL along the gradient (1e-3) and a random direction (2e-2).
+* 512^3 trajectory workload: the forward stages the oracle finishes in a
+  test's time (delta_L, Psi, the redshift-space density and both webs'
+  tensors) against the oracle; the rest through properties that hold at any
+  size: the transform against numpy, mass conservation of the deposit,
+  determinism, agreement of the two likelihood paths, and central differences
+  of the FP64-reduced logL along the gradient (1e-3), a random bias direction
+  (1e-3) and a random direction of nu (sign and size).
 """
 import dataclasses
 import os
@@ -368,3 +371,74 @@ def test_512_invariants():
     anb = float(torch.sum(b1.double() * rb.double()))
     _say("512^3 random bias direction: FD %.6e adjoint %.6e rel %.2e" % (fdb, anb, abs(fdb - anb) / abs(anb)))
     assert abs(fdb - anb) < 1e-3 * abs(anb)
+
+
+class _C4:
+    """The 512^3 trajectory workload (two webs, redshift space along z) at a
+    state near the data's noise: the GPU's forward intermediates, taken once,
+    against the FP64 oracle's stages, computed in the tests that use them."""
+
+    def __init__(self):
+        from oracle import model as om
+        from tests.helpers import oracle_model
+        om.set_workers(16)
+        w = fi.workload("c4")
+        ch = w.chains[0]
+        self.n = ch.n
+        self.nu = fp32(fi.near_truth_noise(ch))
+        self.b = fp32(ch.bias)
+        _say("c4 512^3: GPU forward")
+        p = plan_for(w)
+        p.set_counts(0, dev_counts(fi.timing_counts(ch)))
+        p.forward(dev(self.nu.ravel()), dev(self.b[None]))
+        torch.cuda.synchronize()
+        get = lambda k: p.get_field(0, k).cpu().numpy().reshape((self.n,) * 3)
+        self.gpu = {"dl": get(0), "psi": np.stack([get(k) for k in (1, 2, 3)]), "rho": get(4),
+                    "T": [np.stack([get(6 + 6 * wi + k) for k in range(6)]) for wi in range(2)]}
+        del p
+        torch.cuda.empty_cache()
+        self.m = oracle_model(w, 0)
+        self.psi = None
+
+
+@pytest.fixture(scope="module")
+def c4():
+    return _C4()
+
+
+@pytest.mark.timeout(170)
+def test_c4_full_size_lpt_stages(c4):
+    """512^3: delta_L (the white-noise filter in the 512 mixing pass) and Psi
+    (the six LPT Hessians, the spherical-collapse term and the ALPT blend
+    through the 512 passes) within 1e-5 normwise of the oracle on the same
+    float32 white noise."""
+    _say("c4 512^3: oracle delta_L and ALPT")
+    m = c4.m
+    psi, lpt = m.alpt(m.linear_density_hat(c4.nu.astype(np.float64)))
+    e_dl = relnorm(c4.gpu["dl"], lpt["dl"])
+    del lpt
+    e_psi = relnorm(c4.gpu["psi"], psi)
+    c4.psi = psi
+    c4.gpu["dl"] = c4.gpu["psi"] = None
+    _say("c4 512^3 fields: delta_L=%.2e psi=%.2e" % (e_dl, e_psi))
+    assert e_dl < FIELD_TOL and e_psi < FIELD_TOL
+
+
+@pytest.mark.timeout(170)
+def test_c4_full_size_density_and_tensors(c4):
+    """512^3: the redshift-space density of the sorted deposit (134M
+    particles) and both webs' tensors within 1e-5 normwise of the oracle's,
+    which start from the oracle's own displacement."""
+    if c4.psi is None:
+        pytest.skip("needs the oracle displacement of test_c4_full_size_lpt_stages")
+    m = c4.m
+    _say("c4 512^3: oracle positions and deposit")
+    rho = m.cic(m.positions(c4.psi))
+    c4.psi = None
+    e_rho = relnorm(c4.gpu["rho"], rho)
+    _say("c4 512^3 rho=%.2e; oracle web tensors" % e_rho)
+    tens = m.web_tensors(m.g.rfft(rho - 1.0))
+    del rho
+    e_t = [relnorm(c4.gpu["T"][wi], np.stack(tens[wi])) for wi in range(2)]
+    _say("c4 512^3 fields: rho=%.2e T0=%.2e T1=%.2e" % (e_rho, e_t[0], e_t[1]))
+    assert e_rho < FIELD_TOL and max(e_t) < FIELD_TOL
