@@ -503,39 +503,92 @@ __host__ __device__ constexpr int xy4_cols() {
   return kTile / N > 256 ? 256 : kTile / N;
 }
 
+// Split of the mixing pass's transform: a line of N = 512 is transformed as
+// its even and odd samples, two four-step transforms of 256 on two groups of
+// threads, joined by one radix-2 butterfly across the groups (through LDS).
+// A thread then holds 16 elements instead of 32, which keeps the pass at the
+// register budget of three workgroups per CU (a 512 four-step in one group
+// needs 256 VGPRs and runs one wave per SIMD).
+template <int N>
+__host__ __device__ constexpr int xy4_split() {
+  return N >= 512 ? 2 : 1;
+}
+template <int N>
+__host__ __device__ constexpr int xy4_threads() {
+  return xy4_cols<N>() * xy4_split<N>() * F4<N / xy4_split<N>()>::N1;
+}
+
 // Used for single-mix passes (NMID = 1), where three workgroups per CU fit in
 // registers without spilling; multi-mix passes use the Stockham kernel.
+//
+// With the split (S = 2), thread (g, j) of a column holds in layout A the rows
+// 2 (j + N1 q) + g (sub-line g, the even or odd samples), and in layout B the
+// frequencies (N/2) g + N2 k1 + j + N1 u; the sub-transforms use the
+// 256-point twiddles (every other entry of the 512 table).
 template <int N, int AXIS, int NMID, bool PF>
-__global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1, 3) void xy4_pass_kernel(PassArgs a, const float2* __restrict__ twg) {
-  constexpr int N1 = F4<N>::N1, N2 = F4<N>::N2;
+__global__ __launch_bounds__(xy4_threads<N>(), 3) void xy4_pass_kernel(PassArgs a, const float2* __restrict__ twg) {
+  constexpr int S = xy4_split<N>();
+  constexpr int NS = N / S;                     // length of a sub-line
+  constexpr int N1 = F4<NS>::N1, N2 = F4<NS>::N2;
   constexpr int M = N / 2;
   constexpr int P = pitch_c<N>();
   constexpr int C = xy4_cols<N>();
-  constexpr int NT = C * N1;
-  constexpr int LSZ = f4_lds<N>() + 1;
+  constexpr int NT = xy4_threads<N>();
+  constexpr int LSZ = f4_lds<NS>() + 1;
+  static_assert(S == 1 || 2 * LSZ >= 2 * N1 * N2, "a column's LDS holds the butterfly exchange");
   constexpr long long RS = AXIS == 0 ? (long long)N * P : (long long)P;   // row stride (elements)
   constexpr int ROWB = (int)(RS * 8);                                     // row stride (bytes)
   constexpr int RANGE = (int)(((N - 1) * RS + C) * 8);                   // bytes one workgroup spans
-  __shared__ float2 lds[C * LSZ];
+  __shared__ float2 lds[C * S * LSZ];
   __shared__ float2 tw[N];
+  __shared__ float2 tws[S == 1 ? 1 : NS];       // sub-line twiddles (split only)
   const int t = threadIdx.x;
-  const int c = t % C, j = t / C;
+  const int c = t % C, r = t / C;
+  const int g = r / N1, j = r % N1;             // sub-line and four-step index
   const int c0 = blockIdx.x * C;
   const int b = blockIdx.y;
   const long long chain = blockIdx.z;
   const bool valid = (c0 + c) <= M;
   const long long base = chain * a.chain_stride + (AXIS == 0 ? (long long)b * P : (long long)b * N * P) + c0;
   // lane part of every offset; the row part (a compile-time constant per
-  // element) goes in the scalar offset
-  const int voff = valid ? (int)((j * RS + c) * 8) : kBufOff;
+  // element) goes in the scalar offset.  Layout A rows S (j + N1 q) + g,
+  // layout B rows NS g + N2 (e % N1) + j + N1 (e / N1).
+  const int voff = valid ? (int)(((S * j + g) * RS + c) * 8) : kBufOff;
+  const int voffB = valid ? (int)(((NS * g + j) * RS + c) * 8) : kBufOff;
   for (int i = t; i < N; i += NT) tw[i] = twg[i];
+  if constexpr (S == 2)
+    for (int i = t; i < NS; i += NT) tws[i] = twg[2 * i];
+  const float2* twsub = S == 1 ? tw : tws;
   const int nb = freq_index(b, N);
   const int nz = valid ? c0 + c : 0;
   const int nyq = N / 2;
-  float2* lcol = lds + c * LSZ;
-  // rows held in layout B (register u N1 + k1): N2 (e % N1) + j + N1 (e / N1)
-  auto rowB = [&](int e) { return N2 * (e % N1) + j + N1 * (e / N1); };
+  float2* lcol = lds + (c * S + g) * LSZ;
+  auto rowB = [&](int e) { return NS * g + N2 * (e % N1) + j + N1 * (e / N1); };
   auto rowB_off = [&](int e) { return (N2 * (e % N1) + N1 * (e / N1)) * ROWB; };
+  // radix-2 butterfly across the two sub-lines of a column (split only), in
+  // place on the layout B registers; forward: X[k] = E[k] + w^k O[k] (g = 0)
+  // and X[k + N/2] = E[k] - w^k O[k] (g = 1) from the sub-transforms E, O;
+  // inverse: E = X[k] + X[k + N/2] (g = 0), O = conj(w^k) (X[k] - X[k + N/2])
+  // (g = 1).  Synchronises; all threads must call it.
+  auto butterfly = [&](float2* v, bool inverse) {
+    float2* xc = lds + c * S * LSZ;
+#pragma unroll
+    for (int e = 0; e < N2; ++e) xc[e * 2 * N1 + g * N1 + j] = v[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < N2; ++e) {
+      const float2 o = xc[e * 2 * N1 + (1 - g) * N1 + j];
+      const float2 x0 = g == 0 ? v[e] : o, x1 = g == 0 ? o : v[e];
+      const float2 w = tw[rowB(e) - NS * g];
+      if (!inverse) {
+        const float2 p = cmul(w, x1);
+        v[e] = g == 0 ? cadd(x0, p) : csub(x0, p);
+      } else {
+        v[e] = g == 0 ? cadd(x0, x1) : cmul(cconj(w), csub(x0, x1));
+      }
+    }
+    __syncthreads();
+  };
 
   float2 mid[NMID][N2];
 #pragma unroll
@@ -549,10 +602,10 @@ __global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1, 3) void xy4_pass_kernel(
     const BufRsrc src = buf_rsrc(a.in[i] + base, RANGE);
     if (a.in_fft & (1u << i)) {
 #pragma unroll
-      for (int q = 0; q < N2; ++q) dst[q] = buf_load2(src, voff, N1 * q * ROWB);
+      for (int q = 0; q < N2; ++q) dst[q] = buf_load2(src, voff, S * N1 * q * ROWB);
     } else {
 #pragma unroll
-      for (int e = 0; e < N2; ++e) dst[e] = buf_load2(src, voff, rowB_off(e));
+      for (int e = 0; e < N2; ++e) dst[e] = buf_load2(src, voffB, rowB_off(e));
     }
   };
   // with several inputs, the loads of input i+1 are in flight during the
@@ -576,7 +629,10 @@ __global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1, 3) void xy4_pass_kernel(
     } else {
       load_input(i, val);
     }
-    if (a.in_fft & (1u << i)) fwd_A_to_B<N>(val, lcol, j, tw);
+    if (a.in_fft & (1u << i)) {
+      fwd_A_to_B<NS>(val, lcol, j, twsub);
+      if constexpr (S == 2) butterfly(val, false);
+    }
 #pragma unroll
     for (int m = 0; m < NMID; ++m) {
       const SpecOp op = a.A[m][i];
@@ -641,12 +697,13 @@ __global__ __launch_bounds__(xy4_cols<N>() * F4<N>::N1, 3) void xy4_pass_kernel(
     }
     const BufRsrc dst = buf_rsrc(a.out[o] + base, RANGE);
     if (a.out_fft & (1u << o)) {
-      inv_B_to_A<N>(val, lcol, j, tw);
+      if constexpr (S == 2) butterfly(val, true);
+      inv_B_to_A<NS>(val, lcol, j, twsub);
 #pragma unroll
-      for (int q = 0; q < N2; ++q) buf_store2(dst, voff, N1 * q * ROWB, val[q]);
+      for (int q = 0; q < N2; ++q) buf_store2(dst, voff, S * N1 * q * ROWB, val[q]);
     } else {
 #pragma unroll
-      for (int e = 0; e < N2; ++e) buf_store2(dst, voff, rowB_off(e), val[e]);
+      for (int e = 0; e < N2; ++e) buf_store2(dst, voffB, rowB_off(e), val[e]);
     }
   }
 }
@@ -917,7 +974,7 @@ template <int N>
 static void xyp4(int axis, const PassArgs& a, int chains, const float2* tw, hipStream_t s) {
   constexpr int C = xy4_cols<N>();
   dim3 grid((N / 2 + 1 + C - 1) / C, N, chains);
-  dim3 block(C * F4<N>::N1);
+  dim3 block(xy4_threads<N>());
   const bool pf = a.nin > 1;
   if (axis == 0) {
     if (pf) hipLaunchKernelGGL((xy4_pass_kernel<N, 0, 1, true>), grid, block, 0, s, a, tw);
