@@ -545,9 +545,22 @@ __global__ __launch_bounds__(xy4_threads<N>(), 3) void xy4_pass_kernel(PassArgs 
   const int t = threadIdx.x;
   const int c = t % C, r = t / C;
   const int g = r / N1, j = r % N1;             // sub-line and four-step index
-  const int c0 = blockIdx.x * C;
-  const int b = blockIdx.y;
-  const long long chain = blockIdx.z;
+  // Where a workgroup's C columns cover half of each 128-byte line it reads
+  // (C = 8 at N = 512), the workgroup that reads the other halves runs on the
+  // same XCD right after it: dispatch goes round-robin over the 8 XCDs by
+  // linear workgroup id, so the workgroups 8 ids apart are paired.
+  unsigned bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  if constexpr (C * 8 < 128) {
+    const unsigned gx = gridDim.x, gy = gridDim.y;
+    unsigned lin = bx + gx * (by + gy * bz);
+    if (((gx * gy * gridDim.z) & 15u) == 0u) lin = (lin & ~15u) | ((lin & 7u) << 1) | ((lin >> 3) & 1u);
+    bx = lin % gx;
+    by = (lin / gx) % gy;
+    bz = lin / (gx * gy);
+  }
+  const int c0 = (int)bx * C;
+  const int b = (int)by;
+  const long long chain = bz;
   const bool valid = (c0 + c) <= M;
   const long long base = chain * a.chain_stride + (AXIS == 0 ? (long long)b * P : (long long)b * N * P) + c0;
   // lane part of every offset; the row part (a compile-time constant per
