@@ -2,6 +2,8 @@
 // pointwise terms, cloud-in-cell deposit by counting sort with a gather, its
 // gather adjoint, the fused per-voxel web/bias kernels, the likelihood pass,
 // fixed-order FP64 reductions and the leapfrog updates.
+#include <algorithm>
+
 #include "fzw_device.hpp"
 #include "fzw_ops.hpp"
 
@@ -155,61 +157,75 @@ __device__ __forceinline__ bool cic_locate(const CicArgs& a, int p, int n, int& 
   return ok;
 }
 
-// Adds one to ctr[key] for every lane of the wave that passes `valid`, with
-// one atomic per distinct key in the wave (the particles of a wave sit on one
-// lattice line and land in a few columns).  The lanes are first grouped by key
-// with register-only lane reads; then the first lane of every group issues its
-// group's atomic, all groups in one instruction.  With RET, returns the lane's
-// slot: the counter's old value plus its rank among the lanes of equal key.
-// Every lane of the wave must call it (the grouping loop is wave-uniform).
-template <bool RET>
-__device__ __forceinline__ int wave_count(int* ctr, int key, bool valid) {
-  const int lane = (int)(threadIdx.x & 63);
-  int lead = lane, rank = 0, num = 0;
-  unsigned long long pm = __ballot(valid);
-  while (pm) {
-    const int leader = __ffsll((unsigned long long)pm) - 1;
-    const int lk = __builtin_amdgcn_readlane(key, leader);
-    const bool mine = ((pm >> lane) & 1ull) && key == lk;
-    const unsigned long long mm = __ballot(mine);
-    if (mine) {
-      lead = leader;
-      rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mm, 0u));
-    }
-    if (lane == leader) num = __popcll(mm);
-    pm &= ~mm;
-  }
-  int base = 0;
-  if (valid && lane == lead) {
-    if (RET) base = atomicAdd(ctr + key, num);
-    else atomicAdd(ctr + key, num);
-  }
-  if (RET) base = __shfl(base, lead);
-  return base + rank;
+// The count and the scatter take the particles of a tile of kSrcTile x
+// kSrcTile source columns (all z) per workgroup.  A particle moves a few cells
+// at most, so nearly all of them land in the kWin x kWin destination columns
+// around the tile: those are counted in an LDS histogram over that window, and
+// the workgroup adds each nonzero bin to the column's global counter with one
+// atomic.  A particle that lands outside the window (a displacement above
+// kWinR cells across) uses a global atomic of its own.  Global atomics go from
+// one per distinct column per wavefront to about one per distinct column per
+// tile.
+constexpr int kSrcTile = 2;
+constexpr int kWinR = 6;
+constexpr int kWin = kSrcTile + 2 * kWinR;
+constexpr int kTilePmax = 8;   // particles per thread of a tile at n <= 512
+
+// Window bin of destination column (cx, cy) for the tile at (x0, y0), or -1.
+__device__ __forceinline__ int win_bin(int cx, int cy, int x0, int y0, int n) {
+  int rx = cx - x0 + kWinR, ry = cy - y0 + kWinR;
+  rx += rx < 0 ? n : 0;
+  rx -= rx >= n ? n : 0;
+  ry += ry < 0 ? n : 0;
+  ry -= ry >= n ? n : 0;
+  return rx < kWin && ry < kWin ? rx * kWin + ry : -1;
+}
+// Destination column of window bin `bin`.
+__device__ __forceinline__ int win_key(int bin, int x0, int y0, int n) {
+  int kx = x0 - kWinR + bin / kWin, ky = y0 - kWinR + bin % kWin;
+  kx += kx < 0 ? n : 0;
+  kx -= kx >= n ? n : 0;
+  ky += ky < 0 ? n : 0;
+  ky -= ky >= n ? n : 0;
+  return kx * n + ky;
+}
+// Particle index of entry i of the tile at (x0, y0).
+__device__ __forceinline__ int tile_particle(int i, int x0, int y0, int n) {
+  const int col = i / n, z = i - col * n;
+  return ((x0 + col / kSrcTile) * n + (y0 + col % kSrcTile)) * n + z;
 }
 
 // Particles per destination column (x, y) of the mesh.
 __global__ __launch_bounds__(256) void cic_count_kernel(CicArgs a) {
-  const long long nv = a.nv;
+  __shared__ int hist[kWin * kWin];
   const int n = a.n;
+  const long long nv = a.nv;
   const long long c = blockIdx.y;
   CicArgs b = a;
   for (int d = 0; d < 3; ++d) b.psi[d] = a.psi[d] + c * nv;
   int* count = a.count + c * (long long)n * n;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long p0 = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63u); p0 < nv; p0 += stride) {
-    const long long p = p0 + (threadIdx.x & 63);
-    const bool valid = p < nv;
-    int key = 0;
+  const int t = threadIdx.x;
+  const int tpr = n / kSrcTile, ntile = tpr * tpr;
+  for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    for (int i = t; i < kWin * kWin; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    const int x0 = (tile / tpr) * kSrcTile, y0 = (tile % tpr) * kSrcTile;
     bool bad = false;
-    if (valid) {
+    for (int i = t; i < kSrcTile * kSrcTile * n; i += blockDim.x) {
       int cx, cy, cz;
       float tx, ty, tz;
-      bad = !cic_locate(b, (int)p, n, cx, cy, cz, tx, ty, tz);
-      key = cx * n + cy;
+      bad |= !cic_locate(b, tile_particle(i, x0, y0, n), n, cx, cy, cz, tx, ty, tz);
+      const int bin = win_bin(cx, cy, x0, y0, n);
+      if (bin >= 0) atomicAdd(hist + bin, 1);
+      else atomicAdd(count + cx * n + cy, 1);
     }
-    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(a.flags + c, FZW_NF_STATE);
-    wave_count<false>(count, key, valid);
+    if (__ballot(bad) != 0ull && (t & 63) == 0) atomicOr(a.flags + c, FZW_NF_STATE);
+    __syncthreads();
+    for (int i = t; i < kWin * kWin; i += blockDim.x) {
+      const int h = hist[i];
+      if (h) atomicAdd(count + win_key(i, x0, y0, n), h);
+    }
+    __syncthreads();
   }
 }
 
@@ -299,9 +315,16 @@ __global__ void scan_down_kernel(const int* __restrict__ count, long long nv, co
 
 // Scatter the fractional offsets into column order (any order inside a
 // column); the bucket's y and z indices travel in the .w lane as by << 16 | bz.
+// Per tile (as in the count): the window bins are counted in LDS, each
+// nonzero bin reserves its slots in its column with one global atomic, and the
+// particles take consecutive slots of their bin's range with LDS atomics;
+// particles outside the window take a global slot each.  The located particles
+// stay in registers between the two steps.
 __global__ __launch_bounds__(256) void cic_scatter_kernel(CicArgs a) {
-  const long long nv = a.nv;
+  __shared__ int hist[kWin * kWin];   // counts, then the bins' first slot
+  __shared__ int cur[kWin * kWin];
   const int n = a.n;
+  const long long nv = a.nv;
   const long long c = blockIdx.y;
   const long long ncol = (long long)n * n;
   CicArgs b = a;
@@ -309,19 +332,49 @@ __global__ __launch_bounds__(256) void cic_scatter_kernel(CicArgs a) {
   int* cursor = a.count + c * ncol;
   const int* off = a.offset + c * (ncol + 1);
   float4* sorted = a.sorted + c * nv;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long p0 = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63u); p0 < nv; p0 += stride) {
-    const long long p = p0 + (threadIdx.x & 63);
-    const bool valid = p < nv;
-    int cx = 0, cy = 0, cz = 0;
-    float tx = 0.f, ty = 0.f, tz = 0.f;
-    if (valid) cic_locate(b, (int)p, n, cx, cy, cz, tx, ty, tz);
-    const int key = cx * n + cy;
-    const int slot = wave_count<true>(cursor, key, valid);
-    if (valid) {
-      const int dst = off[key] + slot;
-      if (dst < off[key + 1]) sorted[dst] = make_float4(tx, ty, tz, __int_as_float((cy << 16) | cz));
+  const int t = threadIdx.x;
+  const int tpr = n / kSrcTile, ntile = tpr * tpr;
+  const int per = kSrcTile * kSrcTile * n;
+  for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    for (int i = t; i < kWin * kWin; i += blockDim.x) {
+      hist[i] = 0;
+      cur[i] = 0;
     }
+    __syncthreads();
+    const int x0 = (tile / tpr) * kSrcTile, y0 = (tile % tpr) * kSrcTile;
+    int key[kTilePmax], bin[kTilePmax], yz[kTilePmax];
+    float fx[kTilePmax], fy[kTilePmax], fz[kTilePmax];
+#pragma unroll
+    for (int r = 0; r < kTilePmax; ++r) {
+      const int i = t + r * (int)blockDim.x;
+      bin[r] = -1;
+      key[r] = -1;
+      if (i < per) {
+        int cx, cy, cz;
+        cic_locate(b, tile_particle(i, x0, y0, n), n, cx, cy, cz, fx[r], fy[r], fz[r]);
+        key[r] = cx * n + cy;
+        yz[r] = (cy << 16) | cz;
+        bin[r] = win_bin(cx, cy, x0, y0, n);
+        if (bin[r] >= 0) atomicAdd(hist + bin[r], 1);
+      }
+    }
+    __syncthreads();
+    for (int i = t; i < kWin * kWin; i += blockDim.x) {
+      const int h = hist[i];
+      if (h) {
+        const int k = win_key(i, x0, y0, n);
+        hist[i] = off[k] + atomicAdd(cursor + k, h);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kTilePmax; ++r) {
+      if (key[r] < 0) continue;
+      const int dst = bin[r] >= 0 ? hist[bin[r]] + atomicAdd(cur + bin[r], 1)
+                                  : off[key[r]] + atomicAdd(cursor + key[r], 1);
+      if (dst < off[key[r] + 1]) sorted[dst] = make_float4(fx[r], fy[r], fz[r], __int_as_float(yz[r]));
+    }
+    __syncthreads();
   }
 }
 
@@ -495,7 +548,9 @@ void launch_cic_deposit(const CicArgs& a0, int chains, hipStream_t s) {
   const long long nv = a.nv;
   const long long ncol = (long long)a.n * a.n;
   launch_fill_i32(a.count, ncol * chains, 0, s);
-  dim3 gp(grid_for(nv, 256, 32768), chains);
+  // one workgroup per source tile (kSrcTile^2 columns)
+  const int ntile = (a.n / kSrcTile) * (a.n / kSrcTile);
+  dim3 gp((unsigned)std::min(ntile, 65536), chains);
   hipLaunchKernelGGL(cic_count_kernel, gp, dim3(256), 0, s, a);
   const int nb = (int)((ncol + kScanBlock - 1) / kScanBlock);
   hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb, chains), dim3(256), 0, s, a.count, ncol, a.bsum, nb);
