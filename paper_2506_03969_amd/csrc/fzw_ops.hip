@@ -386,7 +386,11 @@ __global__ __launch_bounds__(256) void cic_scatter_kernel(CicArgs a) {
 // depend on order, so the density is bitwise reproducible and equal to that of
 // the global-atomic deposit below.
 constexpr int kLineTile = 4;
-__global__ __launch_bounds__(256) void cic_gather_tiles_kernel(CicArgs a) {
+// The 4x4-line LDS accumulator (128 KB at N = 256) allows one workgroup per
+// CU, so the workgroup is as wide as a CU takes: 16 wavefronts stream the
+// particles.
+constexpr int kGatherThreads = 1024;
+__global__ __launch_bounds__(kGatherThreads) void cic_gather_tiles_kernel(CicArgs a) {
   extern __shared__ unsigned long long acc_lds[];
   constexpr int T = kLineTile;
   const long long nv = a.nv;
@@ -563,7 +567,7 @@ void launch_cic_deposit(const CicArgs& a0, int chains, hipStream_t s) {
   if (lds > 32768)
     (void)hipFuncSetAttribute((const void*)cic_gather_tiles_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
-  hipLaunchKernelGGL(cic_gather_tiles_kernel, dim3(tiles * tiles, chains), dim3(256), lds, s, a);
+  hipLaunchKernelGGL(cic_gather_tiles_kernel, dim3(tiles * tiles, chains), dim3(kGatherThreads), lds, s, a);
 }
 
 void launch_cic_adjoint(const CicArgs& a0, int chains, hipStream_t s) {
