@@ -500,18 +500,20 @@ __global__ __launch_bounds__(z4_lines<N>() * F4<N / 2>::N1) void lpt_bwd_z4_kern
 // owns column t % C and four-step index j = t / C.
 template <int N>
 __host__ __device__ constexpr int xy4_cols() {
-  return kTile / N > 256 ? 256 : kTile / N;
+  return N == 96 ? 16 : (kTile / N > 256 ? 256 : kTile / N);
 }
 
-// Split of the mixing pass's transform: a line of N = 512 is transformed as
-// its even and odd samples, two four-step transforms of 256 on two groups of
-// threads, joined by one radix-2 butterfly across the groups (through LDS).
-// A thread then holds 16 elements instead of 32, which keeps the pass at the
-// register budget of three workgroups per CU (a 512 four-step in one group
-// needs 256 VGPRs and runs one wave per SIMD).
+// Split of the mixing pass's transform into S sub-lines: a line of N is
+// transformed as its S decimated sub-sequences (samples S p + g), S four-step
+// transforms of N/S on S groups of threads, joined by one radix-S butterfly
+// across the groups (through LDS).  N = 512 (S = 2): a thread holds 16
+// elements instead of 32, which keeps the pass at the register budget of
+// three workgroups per CU (a 512 four-step in one group needs 256 VGPRs and
+// runs one wave per SIMD).  N = 96 (S = 3): three 32-point four-step
+// transforms, where 96 has no register four-step of its own.
 template <int N>
 __host__ __device__ constexpr int xy4_split() {
-  return N >= 512 ? 2 : 1;
+  return N >= 512 ? 2 : (N == 96 ? 3 : 1);
 }
 template <int N>
 __host__ __device__ constexpr int xy4_threads() {
@@ -521,10 +523,10 @@ __host__ __device__ constexpr int xy4_threads() {
 // Used for single-mix passes (NMID = 1), where three workgroups per CU fit in
 // registers without spilling; multi-mix passes use the Stockham kernel.
 //
-// With the split (S = 2), thread (g, j) of a column holds in layout A the rows
-// 2 (j + N1 q) + g (sub-line g, the even or odd samples), and in layout B the
-// frequencies (N/2) g + N2 k1 + j + N1 u; the sub-transforms use the
-// 256-point twiddles (every other entry of the 512 table).
+// With a split into S sub-lines, thread (g, j) of a column holds in layout A
+// the rows S (j + N1 q) + g (sub-line g), and in layout B the frequencies
+// (N/S) g + N2 k1 + j + N1 u; the sub-transforms use the N/S-point twiddles
+// (every S-th entry of the N table).
 template <int N, int AXIS, int NMID, bool PF>
 __global__ __launch_bounds__(xy4_threads<N>(), 3) void xy4_pass_kernel(PassArgs a, const float2* __restrict__ twg) {
   constexpr int S = xy4_split<N>();
@@ -535,7 +537,7 @@ __global__ __launch_bounds__(xy4_threads<N>(), 3) void xy4_pass_kernel(PassArgs 
   constexpr int C = xy4_cols<N>();
   constexpr int NT = xy4_threads<N>();
   constexpr int LSZ = f4_lds<NS>() + 1;
-  static_assert(S == 1 || 2 * LSZ >= 2 * N1 * N2, "a column's LDS holds the butterfly exchange");
+  static_assert(S == 1 || S * LSZ >= S * N1 * N2, "a column's LDS holds the butterfly exchange");
   constexpr long long RS = AXIS == 0 ? (long long)N * P : (long long)P;   // row stride (elements)
   constexpr int ROWB = (int)(RS * 8);                                     // row stride (bytes)
   constexpr int RANGE = (int)(((N - 1) * RS + C) * 8);                   // bytes one workgroup spans
@@ -569,8 +571,8 @@ __global__ __launch_bounds__(xy4_threads<N>(), 3) void xy4_pass_kernel(PassArgs 
   const int voff = valid ? (int)(((S * j + g) * RS + c) * 8) : kBufOff;
   const int voffB = valid ? (int)(((NS * g + j) * RS + c) * 8) : kBufOff;
   for (int i = t; i < N; i += NT) tw[i] = twg[i];
-  if constexpr (S == 2)
-    for (int i = t; i < NS; i += NT) tws[i] = twg[2 * i];
+  if constexpr (S > 1)
+    for (int i = t; i < NS; i += NT) tws[i] = twg[S * i];
   const float2* twsub = S == 1 ? tw : tws;
   const int nb = freq_index(b, N);
   const int nz = valid ? c0 + c : 0;
@@ -578,26 +580,45 @@ __global__ __launch_bounds__(xy4_threads<N>(), 3) void xy4_pass_kernel(PassArgs 
   float2* lcol = lds + (c * S + g) * LSZ;
   auto rowB = [&](int e) { return NS * g + N2 * (e % N1) + j + N1 * (e / N1); };
   auto rowB_off = [&](int e) { return (N2 * (e % N1) + N1 * (e / N1)) * ROWB; };
-  // radix-2 butterfly across the two sub-lines of a column (split only), in
-  // place on the layout B registers; forward: X[k] = E[k] + w^k O[k] (g = 0)
-  // and X[k + N/2] = E[k] - w^k O[k] (g = 1) from the sub-transforms E, O;
-  // inverse: E = X[k] + X[k + N/2] (g = 0), O = conj(w^k) (X[k] - X[k + N/2])
-  // (g = 1).  Synchronises; all threads must call it.
+  // radix-S butterfly across the S sub-lines of a column (split only), in
+  // place on the layout B registers (w = exp(-2 pi i / N), k < N/S).  Forward:
+  // from the sub-transforms Y_h, group g forms X[k + (N/S) g] = sum_h
+  // w^(h k + (N/S) h g) Y_h[k].  Inverse: from X_m[k] = X[k + (N/S) m], held
+  // by group m, it forms Z_g[k] = sum_m conj(w^(g k + (N/S) g m)) X_m[k],
+  // whose N/S-point inverse is sub-line g.  Synchronises; all threads must
+  // call it.
   auto butterfly = [&](float2* v, bool inverse) {
     float2* xc = lds + c * S * LSZ;
 #pragma unroll
-    for (int e = 0; e < N2; ++e) xc[e * 2 * N1 + g * N1 + j] = v[e];
+    for (int e = 0; e < N2; ++e) xc[e * S * N1 + g * N1 + j] = v[e];
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < N2; ++e) {
-      const float2 o = xc[e * 2 * N1 + (1 - g) * N1 + j];
-      const float2 x0 = g == 0 ? v[e] : o, x1 = g == 0 ? o : v[e];
-      const float2 w = tw[rowB(e) - NS * g];
-      if (!inverse) {
-        const float2 p = cmul(w, x1);
-        v[e] = g == 0 ? cadd(x0, p) : csub(x0, p);
+      const int k = rowB(e) - NS * g;
+      if constexpr (S == 2) {
+        // X[k] = Y_0 + w^k Y_1, X[k + N/2] = Y_0 - w^k Y_1; Z_0 = X_0 + X_1,
+        // Z_1 = conj(w^k) (X_0 - X_1)
+        const float2 o = xc[e * 2 * N1 + (1 - g) * N1 + j];
+        const float2 x0 = g == 0 ? v[e] : o, x1 = g == 0 ? o : v[e];
+        const float2 w = tw[k];
+        if (!inverse) {
+          const float2 pr = cmul(w, x1);
+          v[e] = g == 0 ? cadd(x0, pr) : csub(x0, pr);
+        } else {
+          v[e] = g == 0 ? cadd(x0, x1) : cmul(cconj(w), csub(x0, x1));
+        }
       } else {
-        v[e] = g == 0 ? cadd(x0, x1) : cmul(cconj(w), csub(x0, x1));
+        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int h = 0; h < S; ++h) {
+          const float2 y = xc[e * S * N1 + h * N1 + j];
+          const int q = inverse ? g * k + NS * ((g * h) % S) : h * k + NS * ((h * g) % S);
+          const float2 w = tw[q % N];
+          acc = cadd(acc, cmul(inverse ? cconj(w) : w, y));
+        }
+        v[e] = acc;
+        // one element at a time: hoisting every exchange read spills
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     __syncthreads();
@@ -644,7 +665,7 @@ __global__ __launch_bounds__(xy4_threads<N>(), 3) void xy4_pass_kernel(PassArgs 
     }
     if (a.in_fft & (1u << i)) {
       fwd_A_to_B<NS>(val, lcol, j, twsub);
-      if constexpr (S == 2) butterfly(val, false);
+      if constexpr (S > 1) butterfly(val, false);
     }
 #pragma unroll
     for (int m = 0; m < NMID; ++m) {
@@ -710,7 +731,7 @@ __global__ __launch_bounds__(xy4_threads<N>(), 3) void xy4_pass_kernel(PassArgs 
     }
     const BufRsrc dst = buf_rsrc(a.out[o] + base, RANGE);
     if (a.out_fft & (1u << o)) {
-      if constexpr (S == 2) butterfly(val, true);
+      if constexpr (S > 1) butterfly(val, true);
       inv_B_to_A<NS>(val, lcol, j, twsub);
 #pragma unroll
       for (int q = 0; q < N2; ++q) buf_store2(dst, voff, S * N1 * q * ROWB, val[q]);
@@ -1000,11 +1021,9 @@ static void xyp4(int axis, const PassArgs& a, int chains, const float2* tw, hipS
 
 template <int N>
 static void xyp(int axis, const PassArgs& a, int chains, const float2* tw, hipStream_t s) {
-  if constexpr (N != 96) {
-    if (a.nmid == 1 && fft_schedule(N).xy == kSchedFourStep) {
-      xyp4<N>(axis, a, chains, tw, s);
-      return;
-    }
+  if (a.nmid == 1 && fft_schedule(N).xy == kSchedFourStep) {
+    xyp4<N>(axis, a, chains, tw, s);
+    return;
   }
   constexpr int C = xycols<N>();
   dim3 grid((N / 2 + 1 + C - 1) / C, N, chains);

@@ -900,17 +900,15 @@ void tune_fft(fzw_plan* p, Group& g) {
       zi(g, sp0, fin, 1, s);
     });
   }
-  if (has_pure_pass(g.n)) {
-    // a mixing pass with an axis factor and a radial table (the general path)
-    pick(sc.xy, sc.us[1], [&] {
-      Pass ps;
-      ps.in(g.spec[0], true).out(g.spec[1], true);
-      ps.a.A[0][0] = spec(0.f, 1.f, Y, NONE, TAB_INVK2, NONE);
-      ps.a.B[0][0] = spec_const(1.f);
-      run_pass(g, Y, ps, 1, s);
-    });
-    pick(sc.pure, sc.us[2], [&] { pure_xy(g, Y, false, sp0, sp0, 1, s); });
-  }
+  // a mixing pass with an axis factor and a radial table (the general path)
+  pick(sc.xy, sc.us[1], [&] {
+    Pass ps;
+    ps.in(g.spec[0], true).out(g.spec[1], true);
+    ps.a.A[0][0] = spec(0.f, 1.f, Y, NONE, TAB_INVK2, NONE);
+    ps.a.B[0][0] = spec_const(1.f);
+    run_pass(g, Y, ps, 1, s);
+  });
+  if (has_pure_pass(g.n)) pick(sc.pure, sc.us[2], [&] { pure_xy(g, Y, false, sp0, sp0, 1, s); });
   HIPCHK(hipStreamSynchronize(s));
 }
 
