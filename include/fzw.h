@@ -389,9 +389,11 @@ fzw_status fzw_fft_schedule(int mesh_n, int* z, int* xy, int* pure, double* us6)
 /* Set the schedule of a mesh size by hand (each 0 or 1 as above; the tuner
  * then leaves it alone).  Applies to later launches of every plan; a HIP
  * graph captured before keeps the kernels it was captured with.  The 96 mesh
- * has only the Stockham z passes and x/y passes, and the 512 mesh only the
- * Stockham x/y passes, whatever is set.  FZW_E_ARG for an unsupported size or
- * a value other than 0 or 1. */
+ * has only the Stockham z passes and runs its pure x/y transforms through the
+ * mixing kernel, whatever is set; its four-step mixing kernel, like the 512
+ * one, transforms a line as decimated sub-lines (3 of 32, 2 of 256) joined by
+ * one butterfly.  FZW_E_ARG for an unsupported size or a value other than 0
+ * or 1. */
 fzw_status fzw_set_fft_schedule(int mesh_n, int z, int xy, int pure);
 
 /* Kernel classes for per-launch timing.  Every class but the CIC deposit is
