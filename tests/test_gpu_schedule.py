@@ -2,7 +2,8 @@
 Stockham for the z and mixing x/y passes; persistent four-step or the mixing
 kernel for pure x/y transforms), forced one combination at a time: each
 transform against numpy, and the log-likelihood and gradients of a two-web
-case against the FP64 oracle."""
+case against the FP64 oracle.  At 96 only the mixing x/y passes have two
+families (the four-step one splits a line into three 32-point sub-lines)."""
 import itertools
 
 import numpy as np
@@ -22,7 +23,7 @@ from tests.helpers import GRAD_TOL, LOGL_TOL, Floor, fp32, mock_case  # noqa: E4
 COMBOS = list(itertools.product(("four-step", "stockham"), ("four-step", "stockham"), ("four-step", "mixing")))
 
 
-@pytest.mark.parametrize("n", [32, 64, 128])
+@pytest.mark.parametrize("n", [32, 64, 96, 128])
 def test_every_fft_family(n):
     """Each combination against numpy (transforms) and against the FP64
     oracle on the same float32 inputs (logL 1e-4, bias gradient 1e-4
