@@ -456,7 +456,10 @@ __global__ __launch_bounds__(kGatherThreads) void cic_gather_tiles_kernel(CicArg
 }
 
 // Adjoint: each particle gathers the density cotangent at its 8 nodes and
-// writes the displacement cotangent (may alias the displacement buffers).
+// writes the displacement cotangent (may alias the displacement buffers).  A
+// thread takes two particles, p and p + ceil(nv/2), and issues every load of
+// both before its first store: with the output aliasing the input, loads
+// after a store could not be moved ahead of it.
 __global__ void cic_adjoint_kernel(CicArgs a) {
   const long long nv = a.nv;
   const int n = a.n;
@@ -464,37 +467,54 @@ __global__ void cic_adjoint_kernel(CicArgs a) {
   CicArgs b = a;
   for (int d = 0; d < 3; ++d) b.psi[d] = a.psi[d] + c * nv;
   const float* g = a.drho + c * nv;
-  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nv; p += (long long)gridDim.x * blockDim.x) {
-    int cx, cy, cz;
-    float tx, ty, tz;
-    RadialFrame fr;
-    float d0[3];
-    cic_locate<true>(b, (int)p, n, cx, cy, cz, tx, ty, tz, &fr, d0);
-    const int nx = cx + 1 == n ? 0 : cx + 1;
-    const int ny = cy + 1 == n ? 0 : cy + 1;
-    const int nz = cz + 1 == n ? 0 : cz + 1;
-    float gx = 0.f, gy = 0.f, gz = 0.f;
+  const long long half = (nv + 1) / 2;
+  for (long long p0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; p0 < half;
+       p0 += (long long)gridDim.x * blockDim.x) {
+    float gx[2], gy[2], gz[2];
+    RadialFrame fr[2];
+    float d0[2][3];
+    bool has[2];
 #pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
-      const float v = g[((ox ? nx : cx) * n + (oy ? ny : cy)) * (long long)n + (oz ? nz : cz)];
-      const float wx = ox ? tx : 1.f - tx, wy = oy ? ty : 1.f - ty, wz = oz ? tz : 1.f - tz;
-      const float sx = ox ? 1.f : -1.f, sy = oy ? 1.f : -1.f, sz = oz ? 1.f : -1.f;
-      gx += v * sx * wy * wz;
-      gy += v * wx * sy * wz;
-      gz += v * wx * wy * sz;
+    for (int u = 0; u < 2; ++u) {
+      const long long p = p0 + u * half;
+      has[u] = p < nv;
+      int cx, cy, cz;
+      float tx, ty, tz;
+      // the second particle of an odd count repeats the first (not stored)
+      cic_locate<true>(b, (int)(has[u] ? p : p0), n, cx, cy, cz, tx, ty, tz, &fr[u], d0[u]);
+      const int nx = cx + 1 == n ? 0 : cx + 1;
+      const int ny = cy + 1 == n ? 0 : cy + 1;
+      const int nz = cz + 1 == n ? 0 : cz + 1;
+      gx[u] = gy[u] = gz[u] = 0.f;
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
+        const float v = g[((ox ? nx : cx) * n + (oy ? ny : cy)) * (long long)n + (oz ? nz : cz)];
+        const float wx = ox ? tx : 1.f - tx, wy = oy ? ty : 1.f - ty, wz = oz ? tz : 1.f - tz;
+        const float sx = ox ? 1.f : -1.f, sy = oy ? 1.f : -1.f, sz = oz ? 1.f : -1.f;
+        gx[u] += v * sx * wy * wz;
+        gy[u] += v * wx * sy * wz;
+        gz[u] += v * wx * wy * sz;
+      }
     }
-    if (a.radial) {
-      // transpose of ds_i/dd_j = (1+a) delta_ij + r_i (f d_j + (f - 2a) r_j) / |r|^2
-      const float gr = fr.r2 > 0.f ? (gx * fr.rx + gy * fr.ry + gz * fr.rz) / fr.r2 : 0.f;
-      const float f = a.f_los, cr = f - 2.f * fr.a, ca = 1.f + fr.a;
-      gx = ca * gx + gr * (f * d0[0] + cr * fr.rx);
-      gy = ca * gy + gr * (f * d0[1] + cr * fr.ry);
-      gz = ca * gz + gr * (f * d0[2] + cr * fr.rz);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      float x = gx[u], y = gy[u], z = gz[u];
+      if (a.radial) {
+        // transpose of ds_i/dd_j = (1+a) delta_ij + r_i (f d_j + (f - 2a) r_j) / |r|^2
+        const RadialFrame& f0 = fr[u];
+        const float gr = f0.r2 > 0.f ? (x * f0.rx + y * f0.ry + z * f0.rz) / f0.r2 : 0.f;
+        const float f = a.f_los, cr = f - 2.f * f0.a, ca = 1.f + f0.a;
+        x = ca * x + gr * (f * d0[u][0] + cr * f0.rx);
+        y = ca * y + gr * (f * d0[u][1] + cr * f0.ry);
+        z = ca * z + gr * (f * d0[u][2] + cr * f0.rz);
+      }
+      if (!has[u]) continue;
+      const long long p = c * nv + p0 + u * half;
+      a.dpsi[0][p] = x * a.scale[0];
+      a.dpsi[1][p] = y * a.scale[1];
+      a.dpsi[2][p] = z * a.scale[2];
     }
-    a.dpsi[0][c * nv + p] = gx * a.scale[0];
-    a.dpsi[1][c * nv + p] = gy * a.scale[1];
-    a.dpsi[2][c * nv + p] = gz * a.scale[2];
   }
 }
 
